@@ -1,0 +1,190 @@
+"""SNG-DBSCAN CPU oracle -- TEST INFRASTRUCTURE ONLY.
+
+Thin ctypes view of ``libsng_oracle.so`` (plain C, binary64, written from
+Algorithm 1 of the paper; see ``sng_oracle.h`` for the readings it fixes).
+Only the tests, the package smoke check and the benchmark's CPU-baseline leg
+may import this module. The GPU library never links or calls it.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import numpy as np
+
+from . import build as _build
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Load the oracle library, building it first only if nothing is built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_build.LIB):
+        _build.build()
+    lib = ctypes.CDLL(_build.LIB)
+    P = ctypes.c_void_p
+    i64, i32, u64, dbl = ctypes.c_int64, ctypes.c_int32, ctypes.c_uint64, ctypes.c_double
+    lib.sng_oracle_philox4x32_10.argtypes = [P, P, P]
+    lib.sng_oracle_philox4x32_10.restype = None
+    lib.sng_oracle_philox4x64_10.argtypes = [P, P, P]
+    lib.sng_oracle_philox4x64_10.restype = None
+    lib.sng_oracle_samples_per_point.argtypes = [dbl, i64]
+    lib.sng_oracle_samples_per_point.restype = i64
+    lib.sng_oracle_partner.argtypes = [u64, i64, i64, i64]
+    lib.sng_oracle_partner.restype = ctypes.c_uint32
+    lib.sng_oracle_sqdist.argtypes = [P, i64, i32, i64, i64]
+    lib.sng_oracle_sqdist.restype = dbl
+    lib.sng_oracle_degrees_range.argtypes = [P, i64, i32, i64, i64, dbl, u64, i64, i64, P, P]
+    lib.sng_oracle_degrees_range.restype = ctypes.c_int
+    lib.sng_oracle_slot_sqdist.argtypes = [P, i64, i32, i64, i64, u64, i64, i64, P]
+    lib.sng_oracle_slot_sqdist.restype = ctypes.c_int
+    lib.sng_oracle_dbscan.argtypes = [P, i64, i32, i64, i64, dbl, i32, u64, i32, P, P, P]
+    lib.sng_oracle_dbscan.restype = ctypes.c_int
+    lib.sng_oracle_graph.argtypes = [i64, P, i64, i32, P, P, P]
+    lib.sng_oracle_graph.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _ptr(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data
+
+
+class OracleError(RuntimeError):
+    pass
+
+
+def _check(rc: int, what: str):
+    if rc != 0:
+        raise OracleError("%s failed with code %d" % (what, rc))
+
+
+@dataclass
+class Result:
+    labels: np.ndarray   # int32 [n]
+    deg: np.ndarray      # uint32 [n]
+    slots: int
+    self_pairs: int
+    accepted: int
+    n_core: int
+    n_clusters: int
+    n_noise: int
+
+
+def _result(labels, deg, st) -> Result:
+    return Result(labels, deg, int(st[0]), int(st[1]), int(st[2]), int(st[3]), int(st[4]),
+                  int(st[5]))
+
+
+def philox4x32_10(ctr: Sequence[int], key: Sequence[int]) -> np.ndarray:
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    out = np.zeros(4, np.uint32)
+    load().sng_oracle_philox4x32_10(_ptr(c), _ptr(k), _ptr(out))
+    return out
+
+
+def philox4x64_10(ctr: Sequence[int], key: Sequence[int]) -> np.ndarray:
+    c = np.ascontiguousarray(ctr, dtype=np.uint64)
+    k = np.ascontiguousarray(key, dtype=np.uint64)
+    out = np.zeros(4, np.uint64)
+    load().sng_oracle_philox4x64_10(_ptr(c), _ptr(k), _ptr(out))
+    return out
+
+
+def samples_per_point(s: float, n: int) -> int:
+    return int(load().sng_oracle_samples_per_point(float(s), int(n)))
+
+
+def partner(seed: int, n: int, i: int, t: int) -> int:
+    return int(load().sng_oracle_partner(int(seed), int(n), int(i), int(t)))
+
+
+def sqdist(X: np.ndarray, i: int, j: int) -> float:
+    X = _rows(X)
+    return float(load().sng_oracle_sqdist(_ptr(X), X.shape[1], X.shape[1], int(i), int(j)))
+
+
+def _rows(X: np.ndarray) -> np.ndarray:
+    X = np.ascontiguousarray(X, dtype=np.float32)
+    if X.ndim != 2:
+        raise ValueError("X must be [n, d]")
+    return X
+
+
+def degrees(X: np.ndarray, m: int, eps: float, seed: int, i0: int = 0,
+            i1: Optional[int] = None, deg: Optional[np.ndarray] = None):
+    """Sampling step over sources [i0, i1): returns (deg, slots, self, accepted)."""
+    X = _rows(X)
+    n, d = X.shape
+    i1 = n if i1 is None else i1
+    if deg is None:
+        deg = np.zeros(n, np.uint32)
+    st = np.zeros(8, np.uint64)
+    _check(load().sng_oracle_degrees_range(_ptr(X), n, d, d, int(m), float(eps), int(seed),
+                                           int(i0), int(i1), _ptr(deg), _ptr(st)),
+           "sng_oracle_degrees_range")
+    return deg, int(st[0]), int(st[1]), int(st[2])
+
+
+def slot_sqdist(X: np.ndarray, m: int, seed: int, i0: int = 0, i1: Optional[int] = None):
+    X = _rows(X)
+    n, d = X.shape
+    i1 = n if i1 is None else i1
+    out = np.empty((i1 - i0) * int(m), np.float64)
+    _check(load().sng_oracle_slot_sqdist(_ptr(X), n, d, d, int(m), int(seed), int(i0), int(i1),
+                                         _ptr(out)), "sng_oracle_slot_sqdist")
+    return out.reshape(i1 - i0, int(m))
+
+
+def dbscan(X: np.ndarray, eps: float, min_pts: int, seed: int = 0, s: Optional[float] = None,
+           m: Optional[int] = None, exhaustive: bool = False) -> Result:
+    """SNG-DBSCAN (Algorithm 1). Give ``s`` (m = ceil(s*n)) or ``m``;
+    ``exhaustive=True`` uses the full eps-neighbourhood graph instead."""
+    X = _rows(X)
+    n, d = X.shape
+    if not exhaustive:
+        if m is None:
+            m = samples_per_point(s, n)
+            if m < 0:
+                raise OracleError("invalid sampling rate")
+    labels = np.empty(n, np.int32)
+    deg = np.zeros(n, np.uint32)
+    st = np.zeros(8, np.uint64)
+    _check(load().sng_oracle_dbscan(_ptr(X), n, d, d, int(m or 0), float(eps), int(min_pts),
+                                    int(seed), 1 if exhaustive else 0, _ptr(labels), _ptr(deg),
+                                    _ptr(st)), "sng_oracle_dbscan")
+    return _result(labels, deg, st)
+
+
+def graph(n: int, edges, min_pts: int) -> Result:
+    """Post-processing only, on an explicit list of accepted pairs."""
+    e = np.ascontiguousarray(np.asarray(edges, dtype=np.int64).reshape(-1, 2))
+    labels = np.empty(n, np.int32)
+    deg = np.zeros(n, np.uint32)
+    st = np.zeros(8, np.uint64)
+    _check(load().sng_oracle_graph(int(n), _ptr(e), e.shape[0], int(min_pts), _ptr(labels),
+                                   _ptr(deg), _ptr(st)), "sng_oracle_graph")
+    return _result(labels, deg, st)
+
+
+def sweep(X: np.ndarray, eps_grid, min_pts_grid, seed: int, s: Optional[float] = None,
+          m: Optional[int] = None):
+    """Every (eps, MinPts) pair of a grid, each solved by the single-instance
+    definition: labels [P][K][n], degrees [K][n]."""
+    K, P = len(eps_grid), len(min_pts_grid)
+    n = X.shape[0]
+    labels = np.empty((P, K, n), np.int32)
+    degs = np.empty((K, n), np.uint32)
+    for k, e in enumerate(eps_grid):
+        for p, mp in enumerate(min_pts_grid):
+            r = dbscan(X, float(e), int(mp), seed, s=s, m=m)
+            labels[p, k] = r.labels
+            degs[k] = r.deg
+    return labels, degs

@@ -1,0 +1,85 @@
+/*
+ * SNG-DBSCAN CPU oracle -- TEST INFRASTRUCTURE ONLY.
+ *
+ * A plain, slow, obviously correct host implementation of what the SNG-DBSCAN
+ * hot path computes (Jiang, Jang, Lacki, "Faster DBSCAN via subsampled
+ * similarity queries", NeurIPS 2020; Algorithm 1 in Section 3). Only the test
+ * suite, the package smoke check and the benchmark's CPU-baseline leg may load
+ * it. It shares no code, header, table or constant with the GPU library.
+ *
+ * All pointers are host pointers. Floating-point work is binary64, evaluated
+ * in sequential coordinate order, round-to-nearest-even, without contraction
+ * (the library is built with -ffp-contract=off).
+ *
+ * Readings of the paper that fix what Algorithm 1 leaves open (all binding):
+ *  - sampling is with replacement over [0,n); sample t of point i is
+ *        j = Philox4x32-10(ctr = (t/4, i, 0, 0), key = (seed mod 2^32,
+ *            seed / 2^32)) word (t mod 4), reduced mod n,
+ *    for t < m = ceil(fl64(s*n));
+ *  - a self-sample (j == i) adds no edge;
+ *  - the graph is a symmetrised multigraph: every accepted sample adds one to
+ *    the degree of both endpoints, repeated samples count again;
+ *  - a pair is an edge iff D(i,j) <= fl64(eps*eps), D the squared Euclidean
+ *    distance as described above (inclusive, NaN never accepted);
+ *  - core iff (int64)degree >= MinPts;
+ *  - cluster label = smallest point index of the core component; a non-core
+ *    point takes the label of its smallest-index core neighbour, else -1.
+ *
+ * Return codes: 0 on success, -1 on invalid arguments (nothing written),
+ * -2 on a size out of range, -3 on allocation failure.
+ */
+#ifndef SNG_ORACLE_H
+#define SNG_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Philox-4x32 and Philox-4x64 with 10 rounds (Salmon et al., SC'11, Sec. 3). */
+void sng_oracle_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+void sng_oracle_philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]);
+
+/* m = ceil(fl64(s*n)); -1 if s is negative, NaN or infinite, or n < 0. */
+int64_t sng_oracle_samples_per_point(double s, int64_t n);
+
+/* The t-th sampled partner of point i (Algorithm 1, sampling step). */
+uint32_t sng_oracle_partner(uint64_t seed, int64_t n, int64_t i, int64_t t);
+
+/* D(i,j): binary64 squared distance of rows i and j of X (row stride ld). */
+double sng_oracle_sqdist(const float *X, int64_t ld, int32_t d, int64_t i, int64_t j);
+
+/* stats[0..7] = slots, self_pairs, accepted, n_core, n_clusters, n_noise,
+ * 0, 0.  Any of stats/deg may be NULL where noted. */
+
+/* Sampling step over sources [i0, i1): adds the symmetrised degrees into
+ * deg[n] (which the caller zeroes) and counts slots/self/accepted into
+ * stats[0..2] (added). Uses OpenMP threads. */
+int sng_oracle_degrees_range(const float *X, int64_t n, int32_t d, int64_t ld, int64_t m,
+                             double eps, uint64_t seed, int64_t i0, int64_t i1,
+                             uint32_t *deg, uint64_t *stats);
+
+/* D for every slot of sources [i0,i1): out[(i-i0)*m + t]; -1.0 for a
+ * self-sample. */
+int sng_oracle_slot_sqdist(const float *X, int64_t n, int32_t d, int64_t ld, int64_t m,
+                           uint64_t seed, int64_t i0, int64_t i1, double *out);
+
+/* Whole method. mode 0: Philox-sampled graph with m samples per point.
+ * mode 1: exhaustive graph (every unordered pair i<j once; m ignored), i.e.
+ * full DBSCAN on the same post-processing. labels[n] and deg[n] are written;
+ * deg may be NULL. */
+int sng_oracle_dbscan(const float *X, int64_t n, int32_t d, int64_t ld, int64_t m,
+                      double eps, int32_t min_pts, uint64_t seed, int32_t mode,
+                      int32_t *labels, uint32_t *deg, uint64_t *stats);
+
+/* Post-processing only, on an explicit accepted-pair list edges[2*k],
+ * edges[2*k+1] (each pair counted once per occurrence, self-pairs rejected
+ * with -1). */
+int sng_oracle_graph(int64_t n, const int64_t *edges, int64_t n_edges, int32_t min_pts,
+                     int32_t *labels, uint32_t *deg, uint64_t *stats);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
