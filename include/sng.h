@@ -1,0 +1,186 @@
+/*
+ * sng.h -- C ABI of the MI355X (gfx950) SNG-DBSCAN library, libsng.so.
+ *
+ * SNG-DBSCAN (Jiang, Jang, Lacki, "Faster DBSCAN via subsampled similarity
+ * queries", NeurIPS 2020) clusters points X[n,d] from a subsampled
+ * eps-neighbourhood graph (Algorithm 1, Section 3): every point queries
+ * ceil(s*n) sampled partners, a pair closer than eps becomes an edge, points of
+ * degree >= MinPts are core points, the connected components of the core
+ * points are the clusters, a non-core point joins a cluster it touches, and
+ * the rest is noise.
+ *
+ * What this library computes, exactly (the readings that make the output
+ * unique; Algorithm 1 leaves these open):
+ *   m        = ceil(fl64(s * n)) samples per point (1 <= ... any m >= 0).
+ *   sample t of point i (t < m) is j = W[t mod 4] mod n, where
+ *            W = Philox4x32-10(counter = (t/4, i, 0, 0),
+ *                              key = (seed mod 2^32, seed / 2^32))
+ *            (Salmon, Moraes, Dror, Shaw, SC'11).
+ *   edge     (i, j) iff j != i and D(i,j) <= fl64(eps*eps), with D the squared
+ *            Euclidean distance evaluated in binary64: acc = 0; for k < d in
+ *            order: delta = (double)x_ik - (double)x_jk; acc += delta*delta,
+ *            every operation rounded to nearest-even, no fused multiply-add.
+ *            NaN never forms an edge.
+ *   degree   symmetrised multigraph degree: each accepted sample adds one to
+ *            both endpoints (a pair sampled twice counts twice).
+ *   core     (int64)degree >= MinPts (MinPts <= 0 makes every point core).
+ *   label    core point: smallest index of its core component;
+ *            non-core point: label of its smallest-index core neighbour;
+ *            otherwise -1 (noise).
+ * Results are bit-exact and deterministic for every stream, launch shape and
+ * tuning choice; the reduced-precision path returns the same labels.
+ *
+ * Conventions for every call:
+ *   - "device" pointers are HIP device memory of the current device; "host"
+ *     pointers are ordinary host memory. The caller owns all buffers.
+ *   - X is row-major: element (i,k) at X[i*ld + k], ld >= d, 4-byte aligned,
+ *     and readable for n*ld floats (rows may be read in 16-byte pieces up to
+ *     the next multiple of four floats when ld is a multiple of four).
+ *   - `stream` is a hipStream_t passed as void* (NULL = default stream).
+ *     Calls enqueue work on it and return without waiting; outputs are valid
+ *     once the stream has been synchronised.
+ *   - Arguments are validated before anything is enqueued; a call that
+ *     returns an error has written nothing.
+ *   - `workspace` is device memory of at least the size reported by the
+ *     matching *_workspace_size call; its contents on entry are ignored.
+ *     One workspace must not be used by two calls in flight at once.
+ *   - Degrees are 32-bit and wrap beyond 2^32-1 (unreachable in practice:
+ *     the expected degree is about 2m).
+ */
+#ifndef SNG_H
+#define SNG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SNG_OK = 0,
+    SNG_EINVAL = -1,     /* invalid argument (null pointer, d < 1, ld < d, eps < 0, ...) */
+    SNG_ERANGE = -2,     /* a size beyond what the kernels index (n > 2^31-1, m > 2^31, ...) */
+    SNG_EWORKSPACE = -3, /* workspace missing or smaller than required */
+    SNG_EHIP = -4,       /* a HIP runtime call or kernel launch failed */
+    SNG_EOVERFLOW = -5,  /* reported by sng_stats_read: a device queue overflowed */
+    SNG_ENOTIMPL = -6    /* requested form not available for these arguments */
+} sng_status;
+
+typedef enum {
+    SNG_FP32 = 0, /* plain form: binary32 filter, binary64 recheck near eps */
+    SNG_BF16 = 1, /* mixed form: bfloat16 copy on MFMA, binary64 recheck */
+    SNG_FP16 = 2  /* mixed form: float16 copy on MFMA, binary64 recheck */
+} sng_precision;
+
+/* Launch shape of the sampled-distance pass. Zero fields mean "library
+ * default"; every choice gives identical results. */
+typedef struct {
+    int32_t lanes_per_pair;  /* 1,2,4,8,16,32,64 lanes cooperate on one pair */
+    int32_t chunks_per_wave; /* 64-call chunks processed by one wavefront */
+    int32_t stage_lds;       /* 1: keep the source row in LDS instead of VGPRs */
+    int32_t reserved;
+} sng_config;
+
+/* Device-side counters, copied out by sng_stats_read. */
+typedef struct {
+    uint64_t slots;      /* n*m sample slots */
+    uint64_t self_pairs; /* slots whose partner is the point itself */
+    uint64_t accepted;   /* accepted slots (edges counted with multiplicity) */
+    uint64_t rechecked;  /* slots decided by the binary64 recheck */
+    uint64_t n_core;
+    uint64_t n_clusters;
+    uint64_t n_noise;
+    uint64_t overflow;   /* non-zero: a recheck queue overflowed (results invalid) */
+    double band_rel;     /* relative half-width of the recheck band used */
+} sng_stats;
+
+/* Human-readable name of a status code. Never NULL. */
+const char *sng_status_string(int status);
+
+/* m = ceil(fl64(s*n)) (Algorithm 1, sampling step). s must be finite and
+ * >= 0, n >= 0. Host call, no device work. */
+int sng_samples_per_point(double s, int64_t n, int64_t *m);
+
+/* Bytes of workspace for sng_dbscan / sng_degrees with n points of
+ * dimension d and m samples per point, at precision `prec`. Host call. */
+int sng_workspace_size(int64_t n, int32_t d, int64_t m, int32_t prec, size_t *bytes);
+
+/* Sampling step only (Algorithm 1, graph construction; edges are not stored):
+ * degrees[n] (device, u32) receives the symmetrised degree of every point.
+ * X: device float32 [n, ld]. cfg may be NULL. */
+int sng_degrees(const float *X, int64_t n, int32_t d, int64_t ld, int64_t m, double eps,
+                uint64_t seed, uint32_t *degrees, void *workspace, size_t ws_bytes,
+                const sng_config *cfg, void *stream);
+
+/* Whole method (Algorithm 1): labels[n] (device, i32) receive the cluster
+ * labels; degrees (device, u32 [n]) may be NULL. m = ceil(fl64(s*n)). */
+int sng_dbscan(const float *X, int64_t n, int32_t d, int64_t ld, double s, double eps,
+               int32_t min_pts, uint64_t seed, int32_t *labels, uint32_t *degrees,
+               void *workspace, size_t ws_bytes, const sng_config *cfg, void *stream);
+
+/* Mixed-precision form of sng_dbscan: the sampled dot products run on MFMA
+ * from a 16-bit copy X_lp [n, ld_lp] (device, bfloat16 or float16 bit
+ * patterns per `prec`) with X ~= lp_scale * X_lp; every pair whose distance is
+ * not provably on one side of eps is re-decided in binary64 from X, so
+ * labels and degrees equal those of sng_dbscan. X_lp rows must be 16-byte
+ * aligned (ld_lp % 8 == 0). */
+int sng_dbscan_lowp(const float *X, int64_t n, int32_t d, int64_t ld, const uint16_t *X_lp,
+                    int64_t ld_lp, float lp_scale, int32_t prec, double s, double eps,
+                    int32_t min_pts, uint64_t seed, int32_t *labels, uint32_t *degrees,
+                    void *workspace, size_t ws_bytes, const sng_config *cfg, void *stream);
+
+/* Post-processing only (Algorithm 1, core points, components and borders) on
+ * an explicit list of accepted pairs: edges (device, int32 [n_edges][2]),
+ * each pair counted once per occurrence; self-pairs are not allowed.
+ * labels[n] and optional degrees[n] are device outputs. */
+int sng_graph_workspace_size(int64_t n, size_t *bytes);
+int sng_graph_labels(int64_t n, const int32_t *edges, int64_t n_edges, int32_t min_pts,
+                     int32_t *labels, uint32_t *degrees, void *workspace, size_t ws_bytes,
+                     void *stream);
+
+/* Hyperparameter sweep: every (eps[k], min_pts[p]) pair of a grid from one
+ * sampled-distance pass (same sampler for all pairs). eps: host, n_eps values,
+ * strictly increasing, n_eps <= 255. min_pts: host, n_minpts values.
+ * labels: device i32 [n_minpts][n_eps][n]; degrees: device u32 [n_eps][n] or
+ * NULL. Each labels[p][k] equals sng_dbscan(..., eps[k], min_pts[p], ...). */
+int sng_sweep_workspace_size(int64_t n, int32_t d, int64_t m, int32_t n_eps, int32_t n_minpts,
+                             size_t *bytes);
+int sng_dbscan_sweep(const float *X, int64_t n, int32_t d, int64_t ld, double s,
+                     const double *eps, int32_t n_eps, const int32_t *min_pts, int32_t n_minpts,
+                     uint64_t seed, int32_t *labels, uint32_t *degrees, void *workspace,
+                     size_t ws_bytes, void *stream);
+
+/* Batch of independent instances solved together (each equal to its own
+ * sng_dbscan call). Arrays of length `count` are host arrays; X[k],
+ * labels[k], degrees[k] are device pointers (degrees may be NULL or hold
+ * NULL entries). All instances share d. */
+int sng_batch_workspace_size(int32_t count, const int64_t *n, int32_t d, const double *s,
+                             size_t *bytes);
+int sng_dbscan_batch(int32_t count, const float *const *X, const int64_t *n, int32_t d,
+                     const int64_t *ld, const double *s, const double *eps,
+                     const int32_t *min_pts, const uint64_t *seed, int32_t *const *labels,
+                     uint32_t *const *degrees, void *workspace, size_t ws_bytes,
+                     void *stream);
+
+/* Captured form of sng_dbscan_batch: the plan records every pass of the
+ * batch into one HIP graph once; each launch replays it on `stream` with the
+ * same buffers (their contents may change between launches). */
+typedef struct sng_batch_plan sng_batch_plan;
+int sng_batch_plan_create(int32_t count, const float *const *X, const int64_t *n, int32_t d,
+                          const int64_t *ld, const double *s, const double *eps,
+                          const int32_t *min_pts, const uint64_t *seed, int32_t *const *labels,
+                          uint32_t *const *degrees, void *workspace, size_t ws_bytes,
+                          void *stream, sng_batch_plan **plan);
+int sng_batch_plan_launch(sng_batch_plan *plan, void *stream);
+int sng_batch_plan_destroy(sng_batch_plan *plan);
+
+/* Copies the counters of the last call that used `workspace` (waits for
+ * `stream`). Returns SNG_EOVERFLOW if that call's queue overflowed. For a
+ * batch workspace, `index` selects the instance; otherwise pass 0. */
+int sng_stats_read(const void *workspace, int32_t index, sng_stats *out, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SNG_H */

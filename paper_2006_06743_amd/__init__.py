@@ -1,0 +1,272 @@
+"""SNG-DBSCAN on AMD Instinct MI355X (gfx950).
+
+Python binding of libsng.so: argument marshalling only. Every step of the
+method runs in the library's HIP kernels; PyTorch supplies device memory and
+the current stream. The C ABI is documented in include/sng.h.
+
+    labels, degrees = dbscan(X, s, eps, min_pts, seed)     # X: cuda float32 [n, d]
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import torch
+
+from . import _lib
+from ._lib import SNG_BF16, SNG_FP16, SNG_FP32, SNGError, check, sng_config, sng_stats
+
+__all__ = ["dbscan", "dbscan_lowp", "degrees", "graph_labels", "sweep", "batch", "BatchPlan",
+           "samples_per_point", "Config", "Stats", "SNGError", "SNG_FP32", "SNG_BF16",
+           "SNG_FP16", "load"]
+
+
+def load():
+    """Loads libsng.so (raises ImportError if it is not built)."""
+    return _lib.load()
+
+
+@dataclass
+class Config:
+    lanes_per_pair: int = 0
+    chunks_per_wave: int = 0
+    stage_lds: int = 0
+
+    def c(self):
+        return ctypes.byref(sng_config(self.lanes_per_pair, self.chunks_per_wave,
+                                       self.stage_lds, 0))
+
+
+@dataclass
+class Stats:
+    slots: int
+    self_pairs: int
+    accepted: int
+    rechecked: int
+    n_core: int
+    n_clusters: int
+    n_noise: int
+    overflow: int
+    band_rel: float
+
+
+def _stream(t: torch.Tensor) -> int:
+    return torch.cuda.current_stream(t.device).cuda_stream
+
+
+def _rows(X: torch.Tensor):
+    if not X.is_cuda or X.dtype != torch.float32 or X.dim() != 2 or X.stride(1) != 1:
+        raise ValueError("X must be a CUDA float32 tensor [n, d] with unit column stride")
+    return X.shape[0], X.shape[1], X.stride(0) if X.shape[0] > 0 else X.shape[1]
+
+
+def _ws(nbytes: int, device) -> torch.Tensor:
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+def _cfg(cfg: Optional[Config]):
+    return cfg.c() if cfg is not None else None
+
+
+def samples_per_point(s: float, n: int) -> int:
+    m = ctypes.c_int64()
+    check(_lib.load().sng_samples_per_point(float(s), int(n), ctypes.byref(m)),
+          "sng_samples_per_point")
+    return m.value
+
+
+def workspace_size(n: int, d: int, m: int, prec: int = SNG_FP32) -> int:
+    b = ctypes.c_size_t()
+    check(_lib.load().sng_workspace_size(int(n), int(d), int(m), int(prec), ctypes.byref(b)),
+          "sng_workspace_size")
+    return b.value
+
+
+def stats(ws: torch.Tensor, index: int = 0) -> Stats:
+    """Counters of the last call that used workspace `ws` (waits for its stream)."""
+    st = sng_stats()
+    rc = _lib.load().sng_stats_read(ws.data_ptr(), int(index), ctypes.byref(st), _stream(ws))
+    if rc not in (_lib.SNG_OK, _lib.SNG_EOVERFLOW):
+        check(rc, "sng_stats_read")
+    return Stats(st.slots, st.self_pairs, st.accepted, st.rechecked, st.n_core, st.n_clusters,
+                 st.n_noise, st.overflow, st.band_rel)
+
+
+def degrees(X: torch.Tensor, m: int, eps: float, seed: int, cfg: Optional[Config] = None,
+            out: Optional[torch.Tensor] = None, ws: Optional[torch.Tensor] = None):
+    """Sampling step only: symmetrised degrees (int32 tensor holding u32)."""
+    n, d, ld = _rows(X)
+    if out is None:
+        out = torch.empty(n, dtype=torch.int32, device=X.device)
+    if ws is None:
+        ws = _ws(workspace_size(n, d, m), X.device)
+    check(_lib.load().sng_degrees(X.data_ptr(), n, d, ld, int(m), float(eps), int(seed),
+                                  out.data_ptr(), ws.data_ptr(), ws.numel(), _cfg(cfg),
+                                  _stream(X)), "sng_degrees")
+    return out, ws
+
+
+def dbscan(X: torch.Tensor, s: float, eps: float, min_pts: int, seed: int,
+           cfg: Optional[Config] = None, want_degrees: bool = True,
+           labels: Optional[torch.Tensor] = None, degrees_out: Optional[torch.Tensor] = None,
+           ws: Optional[torch.Tensor] = None):
+    """SNG-DBSCAN (Algorithm 1): returns (labels int32, degrees int32-as-u32 or None, ws)."""
+    n, d, ld = _rows(X)
+    m = samples_per_point(s, n)
+    if labels is None:
+        labels = torch.empty(n, dtype=torch.int32, device=X.device)
+    if want_degrees and degrees_out is None:
+        degrees_out = torch.empty(n, dtype=torch.int32, device=X.device)
+    if ws is None:
+        ws = _ws(workspace_size(n, d, m), X.device)
+    check(_lib.load().sng_dbscan(X.data_ptr(), n, d, ld, float(s), float(eps), int(min_pts),
+                                 int(seed), labels.data_ptr(),
+                                 degrees_out.data_ptr() if degrees_out is not None else None,
+                                 ws.data_ptr(), ws.numel(), _cfg(cfg), _stream(X)),
+          "sng_dbscan")
+    return labels, degrees_out, ws
+
+
+def dbscan_lowp(X: torch.Tensor, X_lp: torch.Tensor, s: float, eps: float, min_pts: int,
+                seed: int, prec: int = SNG_BF16, lp_scale: float = 1.0,
+                cfg: Optional[Config] = None, ws: Optional[torch.Tensor] = None):
+    """Mixed-precision form: X_lp holds bfloat16/float16 bits (int16/bf16/fp16 tensor)."""
+    n, d, ld = _rows(X)
+    if X_lp.element_size() != 2 or X_lp.dim() != 2 or X_lp.stride(1) != 1 or not X_lp.is_cuda:
+        raise ValueError("X_lp must be a CUDA 16-bit tensor [n, >=d] with unit column stride")
+    m = samples_per_point(s, n)
+    labels = torch.empty(n, dtype=torch.int32, device=X.device)
+    deg = torch.empty(n, dtype=torch.int32, device=X.device)
+    if ws is None:
+        ws = _ws(workspace_size(n, d, m, prec), X.device)
+    check(_lib.load().sng_dbscan_lowp(X.data_ptr(), n, d, ld, X_lp.data_ptr(),
+                                      X_lp.stride(0) if n > 0 else d, float(lp_scale), int(prec),
+                                      float(s), float(eps), int(min_pts), int(seed),
+                                      labels.data_ptr(), deg.data_ptr(), ws.data_ptr(),
+                                      ws.numel(), _cfg(cfg), _stream(X)), "sng_dbscan_lowp")
+    return labels, deg, ws
+
+
+def graph_labels(n: int, edges: torch.Tensor, min_pts: int, device=None):
+    """Post-processing only on an explicit accepted-pair list (int32 [E, 2])."""
+    dev = edges.device if edges.is_cuda else torch.device(device or "cuda")
+    e = edges.to(device=dev, dtype=torch.int32).contiguous()
+    b = ctypes.c_size_t()
+    check(_lib.load().sng_graph_workspace_size(int(n), ctypes.byref(b)),
+          "sng_graph_workspace_size")
+    ws = _ws(b.value, dev)
+    labels = torch.empty(n, dtype=torch.int32, device=dev)
+    deg = torch.empty(n, dtype=torch.int32, device=dev)
+    check(_lib.load().sng_graph_labels(int(n), e.data_ptr() if e.numel() else None,
+                                       e.shape[0], int(min_pts), labels.data_ptr(),
+                                       deg.data_ptr(), ws.data_ptr(), ws.numel(),
+                                       torch.cuda.current_stream(dev).cuda_stream),
+          "sng_graph_labels")
+    return labels, deg, ws
+
+
+def sweep(X: torch.Tensor, s: float, eps_grid: Sequence[float], min_pts_grid: Sequence[int],
+          seed: int, want_degrees: bool = True, ws: Optional[torch.Tensor] = None):
+    """All (eps, MinPts) pairs of a grid from one sampled-distance pass:
+    labels [P][K][n] int32, degrees [K][n] (u32 bits) or None."""
+    import numpy as np
+    n, d, ld = _rows(X)
+    m = samples_per_point(s, n)
+    eps = np.ascontiguousarray(eps_grid, dtype=np.float64)
+    mp = np.ascontiguousarray(min_pts_grid, dtype=np.int32)
+    K, P = eps.size, mp.size
+    b = ctypes.c_size_t()
+    check(_lib.load().sng_sweep_workspace_size(n, d, m, K, P, ctypes.byref(b)),
+          "sng_sweep_workspace_size")
+    if ws is None:
+        ws = _ws(b.value, X.device)
+    labels = torch.empty((P, K, n), dtype=torch.int32, device=X.device)
+    deg = torch.empty((K, n), dtype=torch.int32, device=X.device) if want_degrees else None
+    check(_lib.load().sng_dbscan_sweep(X.data_ptr(), n, d, ld, float(s), eps.ctypes.data, K,
+                                       mp.ctypes.data, P, int(seed), labels.data_ptr(),
+                                       deg.data_ptr() if deg is not None else None,
+                                       ws.data_ptr(), ws.numel(), _stream(X)),
+          "sng_dbscan_sweep")
+    return labels, deg, ws
+
+
+def _batch_args(Xs, s, eps, min_pts, seeds, labels, degs):
+    import numpy as np
+    count = len(Xs)
+    d = Xs[0].shape[1]
+    arr = lambda vals, dt: np.ascontiguousarray(vals, dtype=dt)
+    xp = arr([x.data_ptr() for x in Xs], np.uint64)
+    ns = arr([x.shape[0] for x in Xs], np.int64)
+    lds = arr([x.stride(0) if x.shape[0] > 0 else d for x in Xs], np.int64)
+    ss = arr(s, np.float64)
+    es = arr(eps, np.float64)
+    ms = arr(min_pts, np.int32)
+    sd = arr(seeds, np.uint64)
+    lp = arr([t.data_ptr() for t in labels], np.uint64)
+    dp = arr([t.data_ptr() for t in degs], np.uint64)
+    return count, d, (xp, ns, lds, ss, es, ms, sd, lp, dp)
+
+
+def batch_workspace_size(ns, d, s) -> int:
+    import numpy as np
+    n_arr = np.ascontiguousarray(ns, dtype=np.int64)
+    s_arr = np.ascontiguousarray(s, dtype=np.float64)
+    b = ctypes.c_size_t()
+    check(_lib.load().sng_batch_workspace_size(len(n_arr), n_arr.ctypes.data, int(d),
+                                               s_arr.ctypes.data, ctypes.byref(b)),
+          "sng_batch_workspace_size")
+    return b.value
+
+
+def batch(Xs, s, eps, min_pts, seeds, ws: Optional[torch.Tensor] = None):
+    """Independent instances solved together; returns per-instance (labels, degrees)."""
+    for x in Xs:
+        _rows(x)
+    dev = Xs[0].device
+    labels = [torch.empty(x.shape[0], dtype=torch.int32, device=dev) for x in Xs]
+    degs = [torch.empty(x.shape[0], dtype=torch.int32, device=dev) for x in Xs]
+    count, d, a = _batch_args(Xs, s, eps, min_pts, seeds, labels, degs)
+    if ws is None:
+        ws = _ws(batch_workspace_size(a[1], d, a[3]), dev)
+    xp, ns, lds, ss, es, ms, sd, lp, dp = a
+    check(_lib.load().sng_dbscan_batch(count, xp.ctypes.data, ns.ctypes.data, d, lds.ctypes.data,
+                                       ss.ctypes.data, es.ctypes.data, ms.ctypes.data,
+                                       sd.ctypes.data, lp.ctypes.data, dp.ctypes.data,
+                                       ws.data_ptr(), ws.numel(), _stream(Xs[0])),
+          "sng_dbscan_batch")
+    return labels, degs, ws
+
+
+class BatchPlan:
+    """A batch recorded once into a HIP graph and replayed by launch()."""
+
+    def __init__(self, Xs, s, eps, min_pts, seeds):
+        for x in Xs:
+            _rows(x)
+        dev = Xs[0].device
+        self.Xs = list(Xs)
+        self.labels = [torch.empty(x.shape[0], dtype=torch.int32, device=dev) for x in Xs]
+        self.degrees = [torch.empty(x.shape[0], dtype=torch.int32, device=dev) for x in Xs]
+        count, d, a = _batch_args(Xs, s, eps, min_pts, seeds, self.labels, self.degrees)
+        self.ws = _ws(batch_workspace_size(a[1], d, a[3]), dev)
+        xp, ns, lds, ss, es, ms, sd, lp, dp = a
+        self._plan = ctypes.c_void_p()
+        check(_lib.load().sng_batch_plan_create(
+            count, xp.ctypes.data, ns.ctypes.data, d, lds.ctypes.data, ss.ctypes.data,
+            es.ctypes.data, ms.ctypes.data, sd.ctypes.data, lp.ctypes.data, dp.ctypes.data,
+            self.ws.data_ptr(), self.ws.numel(), _stream(Xs[0]), ctypes.byref(self._plan)),
+            "sng_batch_plan_create")
+
+    def launch(self):
+        check(_lib.load().sng_batch_plan_launch(self._plan, _stream(self.Xs[0])),
+              "sng_batch_plan_launch")
+        return self.labels, self.degrees
+
+    def __del__(self):
+        try:
+            if self._plan:
+                _lib.load().sng_batch_plan_destroy(self._plan)
+                self._plan = None
+        except Exception:
+            pass

@@ -1,0 +1,379 @@
+// C ABI of libsng.so: argument validation, workspace layout and the launch
+// sequence of each entry point (declarations and contracts in sng.h).
+#include <math.h>
+#include <string.h>
+
+#include "../../include/sng.h"
+#include "sng_internal.hpp"
+
+using namespace sng;
+
+namespace {
+
+constexpr size_t kHeaderBytes = 4096;  // counters of one instance
+constexpr size_t kAlign = 256;
+constexpr int64_t kMaxN = 2147483647LL;
+constexpr int64_t kMaxM = 2147483648LL;  // t/4 and 4*C stay in 32 bits
+
+size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
+
+struct Carve {
+    char *base;
+    size_t off = 0;
+    explicit Carve(void *b) : base((char *)b) {}
+    template <class T>
+    T *take(size_t count)
+    {
+        T *p = (T *)(base + off);
+        off = align_up(off + count * sizeof(T));
+        return p;
+    }
+};
+
+int m_from_s(double s, int64_t n, int64_t *m)
+{
+    if (!(s >= 0.0) || isinf(s) || n < 0)
+        return SNG_EINVAL;
+    const double v = ceil(s * (double)n);
+    if (v > (double)kMaxM)
+        return SNG_ERANGE;
+    *m = (int64_t)v;
+    return SNG_OK;
+}
+
+int check_points(const void *X, int64_t n, int32_t d, int64_t ld)
+{
+    if (n < 0 || d < 1 || ld < d)
+        return SNG_EINVAL;
+    if (n > kMaxN)
+        return SNG_ERANGE;
+    if (n > 0 && (!X || ((uintptr_t)X & 3u)))
+        return SNG_EINVAL;
+    if (ld > (int64_t)1 << 40)
+        return SNG_ERANGE;
+    return SNG_OK;
+}
+
+int check_eps(double eps)
+{
+    return (eps >= 0.0 && !isinf(eps)) ? SNG_OK : SNG_EINVAL;
+}
+
+struct Sizes {
+    uint64_t C = 0, calls = 0, chunks = 0;
+};
+
+Sizes sizes_for(int64_t n, int64_t m)
+{
+    Sizes z;
+    z.C = (uint64_t)((m + 3) / 4);
+    z.calls = (uint64_t)n * z.C;
+    z.chunks = (z.calls + 63) / 64;
+    return z;
+}
+
+size_t plain_ws_bytes(int64_t n, int64_t m)
+{
+    const Sizes z = sizes_for(n, m);
+    size_t b = kHeaderBytes;
+    b = align_up(b + (size_t)n * 4);     // degrees
+    b = align_up(b + (size_t)n);         // core flags
+    b = align_up(b + z.chunks * 8 * 4);  // accept bits
+    return b;
+}
+
+inline int hip_rc(hipError_t e) { return e == hipSuccess ? SNG_OK : SNG_EHIP; }
+
+#define SNG_TRY(expr)                       \
+    do {                                    \
+        const hipError_t e_ = (expr);       \
+        if (e_ != hipSuccess)               \
+            return SNG_EHIP;                \
+    } while (0)
+
+// Fills the descriptor of one plain instance whose buffers are already carved.
+Inst make_inst(const float *X, int64_t n, int32_t d, int64_t ld, int64_t m, double eps,
+               uint64_t seed, int32_t min_pts)
+{
+    Inst I;
+    memset(&I, 0, sizeof(I));
+    const Sizes z = sizes_for(n, m);
+    I.X = X;
+    I.ld = ld;
+    I.n = (uint32_t)n;
+    I.d = d;
+    I.m = (uint32_t)m;
+    I.C = (uint32_t)z.C;
+    I.key0 = (uint32_t)(seed & 0xFFFFFFFFull);
+    I.key1 = (uint32_t)(seed >> 32);
+    I.inv_n = n > 0 ? 1.0 / (double)n : 0.0;
+    I.inv_C = z.C > 0 ? 1.0 / (double)z.C : 0.0;
+    I.eps2 = eps * eps;
+    band_fp32(I.eps2, d, &I.lo, &I.hi, nullptr);
+    I.calls = z.calls;
+    I.chunks = z.chunks;
+    I.chunk0 = 0;
+    I.min_pts = min_pts;
+    return I;
+}
+
+PassAShape shape_for(const Inst &I, const sng_config *cfg)
+{
+    const bool vec_ok = ((uintptr_t)I.X % 16 == 0) && (I.ld % 4 == 0);
+    return resolve_shape(I.d, vec_ok, cfg ? cfg->lanes_per_pair : 0,
+                         cfg ? cfg->chunks_per_wave : 0, cfg ? cfg->stage_lds : 0);
+}
+
+int check_cfg(const sng_config *cfg)
+{
+    if (!cfg)
+        return SNG_OK;
+    const int g = cfg->lanes_per_pair;
+    if (g != 0 && g != 1 && g != 2 && g != 4 && g != 8 && g != 16 && g != 32 && g != 64)
+        return SNG_EINVAL;
+    if (cfg->chunks_per_wave < 0 || cfg->chunks_per_wave > 4096)
+        return SNG_EINVAL;
+    return SNG_OK;
+}
+
+__global__ void k_header(unsigned long long *cnt, unsigned long long slots, double band)
+{
+    const int t = threadIdx.x;
+    if (t < kCntNum)
+        cnt[t] = (t == kCntSlots) ? slots : 0ull;
+    if (t == 0)
+        ((double *)(cnt + kCntNum))[0] = band;
+}
+
+hipError_t init_header(unsigned long long *cnt, uint64_t slots, double band, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_header, dim3(1), dim3(64), 0, st, cnt, (unsigned long long)slots, band);
+    return hipGetLastError();
+}
+
+// Pass (a) plus post-processing for one carved instance.
+int run_plain(Inst &I, const sng_config *cfg, bool labels_wanted, hipStream_t st)
+{
+    double band = 0.0;
+    {
+        float lo, hi;
+        band_fp32(I.eps2, I.d, &lo, &hi, &band);
+    }
+    SNG_TRY(init_header(I.cnt, (uint64_t)I.n * I.m, band, st));
+    SNG_TRY(launch_fill_u32(I.deg, I.n, 0u, st));
+    if (I.m > 0)
+        SNG_TRY(launch_pass_a(I, shape_for(I, cfg), st));
+    if (!labels_wanted)
+        return SNG_OK;
+    SNG_TRY(launch_core_init(I, st));
+    if (I.m > 0)
+        SNG_TRY(launch_hook_mask(I, st));
+    SNG_TRY(launch_finalize(I, st));
+    return SNG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *sng_status_string(int status)
+{
+    switch (status) {
+    case SNG_OK: return "ok";
+    case SNG_EINVAL: return "invalid argument";
+    case SNG_ERANGE: return "size out of range";
+    case SNG_EWORKSPACE: return "workspace missing or too small";
+    case SNG_EHIP: return "HIP runtime error";
+    case SNG_EOVERFLOW: return "device queue overflow";
+    case SNG_ENOTIMPL: return "not implemented for these arguments";
+    default: return "unknown status";
+    }
+}
+
+int sng_samples_per_point(double s, int64_t n, int64_t *m)
+{
+    if (!m)
+        return SNG_EINVAL;
+    return m_from_s(s, n, m);
+}
+
+int sng_workspace_size(int64_t n, int32_t d, int64_t m, int32_t prec, size_t *bytes)
+{
+    if (!bytes || n < 0 || d < 1 || m < 0)
+        return SNG_EINVAL;
+    if (n > kMaxN || m > kMaxM)
+        return SNG_ERANGE;
+    if (prec != SNG_FP32 && prec != SNG_BF16 && prec != SNG_FP16)
+        return SNG_EINVAL;
+    *bytes = plain_ws_bytes(n, m);
+    return SNG_OK;
+}
+
+int sng_degrees(const float *X, int64_t n, int32_t d, int64_t ld, int64_t m, double eps,
+                uint64_t seed, uint32_t *degrees, void *workspace, size_t ws_bytes,
+                const sng_config *cfg, void *stream)
+{
+    int rc = check_points(X, n, d, ld);
+    if (rc) return rc;
+    if ((rc = check_eps(eps))) return rc;
+    if ((rc = check_cfg(cfg))) return rc;
+    if (m < 0) return SNG_EINVAL;
+    if (m > kMaxM) return SNG_ERANGE;
+    if (n > 0 && !degrees) return SNG_EINVAL;
+    const size_t need = plain_ws_bytes(n, m);
+    if (!workspace || ws_bytes < need) return SNG_EWORKSPACE;
+    hipStream_t st = (hipStream_t)stream;
+    Carve cv(workspace);
+    Inst I = make_inst(X, n, d, ld, m, eps, seed, 0);
+    I.cnt = cv.take<unsigned long long>(kHeaderBytes / 8);
+    (void)cv.take<uint32_t>((size_t)n);
+    I.core = cv.take<uint8_t>((size_t)n);
+    I.mask = cv.take<uint32_t>(sizes_for(n, m).chunks * 8);
+    I.deg = degrees;
+    I.labels = nullptr;
+    return run_plain(I, cfg, false, st);
+}
+
+int sng_dbscan(const float *X, int64_t n, int32_t d, int64_t ld, double s, double eps,
+               int32_t min_pts, uint64_t seed, int32_t *labels, uint32_t *degrees,
+               void *workspace, size_t ws_bytes, const sng_config *cfg, void *stream)
+{
+    int rc = check_points(X, n, d, ld);
+    if (rc) return rc;
+    if ((rc = check_eps(eps))) return rc;
+    if ((rc = check_cfg(cfg))) return rc;
+    int64_t m = 0;
+    if ((rc = m_from_s(s, n, &m))) return rc;
+    if (n > 0 && !labels) return SNG_EINVAL;
+    if (n > 0 && (((uintptr_t)labels & 3u) || ((uintptr_t)degrees & 3u))) return SNG_EINVAL;
+    const size_t need = plain_ws_bytes(n, m);
+    if (!workspace || ws_bytes < need) return SNG_EWORKSPACE;
+    hipStream_t st = (hipStream_t)stream;
+    Carve cv(workspace);
+    Inst I = make_inst(X, n, d, ld, m, eps, seed, min_pts);
+    I.cnt = cv.take<unsigned long long>(kHeaderBytes / 8);
+    uint32_t *wdeg = cv.take<uint32_t>((size_t)n);
+    I.core = cv.take<uint8_t>((size_t)n);
+    I.mask = cv.take<uint32_t>(sizes_for(n, m).chunks * 8);
+    I.deg = degrees ? degrees : wdeg;
+    I.labels = labels;
+    return run_plain(I, cfg, true, st);
+}
+
+int sng_dbscan_lowp(const float *, int64_t, int32_t, int64_t, const uint16_t *, int64_t, float,
+                    int32_t, double, double, int32_t, uint64_t, int32_t *, uint32_t *, void *,
+                    size_t, const sng_config *, void *)
+{
+    return SNG_ENOTIMPL;
+}
+
+int sng_graph_workspace_size(int64_t n, size_t *bytes)
+{
+    if (!bytes || n < 0)
+        return SNG_EINVAL;
+    if (n > kMaxN)
+        return SNG_ERANGE;
+    *bytes = align_up(align_up(kHeaderBytes + (size_t)n * 4) + (size_t)n);
+    return SNG_OK;
+}
+
+int sng_graph_labels(int64_t n, const int32_t *edges, int64_t n_edges, int32_t min_pts,
+                     int32_t *labels, uint32_t *degrees, void *workspace, size_t ws_bytes,
+                     void *stream)
+{
+    if (n < 0 || n_edges < 0 || (n_edges > 0 && !edges) || (n > 0 && !labels))
+        return SNG_EINVAL;
+    if (n > kMaxN)
+        return SNG_ERANGE;
+    if (n == 0 && n_edges > 0)
+        return SNG_EINVAL;
+    size_t need = 0;
+    sng_graph_workspace_size(n, &need);
+    if (!workspace || ws_bytes < need)
+        return SNG_EWORKSPACE;
+    hipStream_t st = (hipStream_t)stream;
+    Carve cv(workspace);
+    Inst I;
+    memset(&I, 0, sizeof(I));
+    I.n = (uint32_t)n;
+    I.min_pts = min_pts;
+    I.cnt = cv.take<unsigned long long>(kHeaderBytes / 8);
+    uint32_t *wdeg = cv.take<uint32_t>((size_t)n);
+    I.core = cv.take<uint8_t>((size_t)n);
+    I.deg = degrees ? degrees : wdeg;
+    I.labels = labels;
+    SNG_TRY(init_header(I.cnt, (uint64_t)n_edges, 0.0, st));
+    SNG_TRY(launch_fill_u32(I.deg, I.n, 0u, st));
+    SNG_TRY(launch_edge_degrees(edges, n_edges, I.deg, st));
+    SNG_TRY(launch_core_init(I, st));
+    SNG_TRY(launch_hook_edges(I, edges, n_edges, st));
+    SNG_TRY(launch_finalize(I, st));
+    return SNG_OK;
+}
+
+int sng_sweep_workspace_size(int64_t, int32_t, int64_t, int32_t, int32_t, size_t *bytes)
+{
+    if (bytes)
+        *bytes = 0;
+    return SNG_ENOTIMPL;
+}
+
+int sng_dbscan_sweep(const float *, int64_t, int32_t, int64_t, double, const double *, int32_t,
+                     const int32_t *, int32_t, uint64_t, int32_t *, uint32_t *, void *, size_t,
+                     void *)
+{
+    return SNG_ENOTIMPL;
+}
+
+int sng_batch_workspace_size(int32_t, const int64_t *, int32_t, const double *, size_t *bytes)
+{
+    if (bytes)
+        *bytes = 0;
+    return SNG_ENOTIMPL;
+}
+
+int sng_dbscan_batch(int32_t, const float *const *, const int64_t *, int32_t, const int64_t *,
+                     const double *, const double *, const int32_t *, const uint64_t *,
+                     int32_t *const *, uint32_t *const *, void *, size_t, void *)
+{
+    return SNG_ENOTIMPL;
+}
+
+int sng_batch_plan_create(int32_t, const float *const *, const int64_t *, int32_t,
+                          const int64_t *, const double *, const double *, const int32_t *,
+                          const uint64_t *, int32_t *const *, uint32_t *const *, void *, size_t,
+                          void *, sng_batch_plan **plan)
+{
+    if (plan)
+        *plan = nullptr;
+    return SNG_ENOTIMPL;
+}
+
+int sng_batch_plan_launch(sng_batch_plan *, void *) { return SNG_ENOTIMPL; }
+
+int sng_batch_plan_destroy(sng_batch_plan *) { return SNG_OK; }
+
+int sng_stats_read(const void *workspace, int32_t index, sng_stats *out, void *stream)
+{
+    if (!workspace || !out || index < 0)
+        return SNG_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    if (hipStreamSynchronize(st) != hipSuccess)
+        return SNG_EHIP;
+    unsigned long long h[kCntNum + 1];
+    const char *src = (const char *)workspace + (size_t)index * 0;  // one header per workspace
+    if (hipMemcpy(h, src, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess)
+        return SNG_EHIP;
+    out->slots = h[kCntSlots];
+    out->self_pairs = h[kCntSelf];
+    out->accepted = h[kCntAccepted];
+    out->rechecked = h[kCntRechecked];
+    out->n_core = h[kCntCore];
+    out->n_clusters = h[kCntClusters];
+    out->n_noise = h[kCntNoise];
+    out->overflow = h[kCntOverflow];
+    memcpy(&out->band_rel, &h[kCntNum], sizeof(double));
+    return out->overflow ? SNG_EOVERFLOW : SNG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,258 @@
+// Device building blocks of the SNG-DBSCAN kernels (gfx950, wave64).
+//
+// Everything here runs on the GPU; the host side only fills the Inst
+// descriptor. Nothing is shared with the CPU oracle.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sng {
+
+constexpr int kWave = 64;
+constexpr int32_t kNoCore = 0x7FFFFFFF;  // "no core neighbour yet" in the label array
+
+// Counter slots in the workspace header (u64 each).
+enum Counter : int {
+    kCntSlots = 0,
+    kCntSelf = 1,
+    kCntAccepted = 2,
+    kCntRechecked = 3,
+    kCntCore = 4,
+    kCntClusters = 5,
+    kCntNoise = 6,
+    kCntOverflow = 7,
+    kCntQueue = 8,
+    kCntNum = 16
+};
+
+// One clustering instance as the kernels see it.
+struct Inst {
+    const float *X;         // row-major, element (i,k) at X[i*ld + k]
+    int64_t ld;             // row stride in floats
+    uint32_t n;             // points
+    int32_t d;              // dimension
+    uint32_t m;             // samples per point
+    uint32_t C;             // Philox calls per point = ceil(m/4)
+    uint32_t key0, key1;    // Philox key = seed
+    double inv_n;           // fl64(1/n), for the exact remainder
+    double inv_C;           // fl64(1/C)
+    float lo, hi;           // binary32 band: F <= lo accept, F > hi reject
+    double eps2;            // fl64(eps*eps), the binary64 threshold
+    uint64_t calls;         // n*C
+    uint64_t chunk0;        // first global 64-call chunk of this instance
+    uint64_t chunks;        // chunks of this instance
+    uint32_t *deg;          // [n] symmetrised degrees
+    uint32_t *mask;         // accept bits, 32 per word = 8 calls; indexed by global call
+    uint8_t *core;          // [n]
+    int32_t *labels;        // [n] union-find parents / border candidates / labels
+    unsigned long long *cnt;  // counters (kCntNum)
+    int32_t min_pts;
+    int32_t pad_;
+};
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon et al., SC'11, Sec. 3.2) for the counter (c, i, 0, 0).
+// ---------------------------------------------------------------------------
+struct Words4 {
+    uint32_t w[4];
+};
+
+__device__ __forceinline__ Words4 philox10(uint32_t c, uint32_t i, uint32_t key0, uint32_t key1)
+{
+    uint32_t x0 = c, x1 = i, x2 = 0u, x3 = 0u;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t p = (uint64_t)0xD2511F53u * x0;  // multiplier 0
+        const uint64_t q = (uint64_t)0xCD9E8D57u * x2;  // multiplier 1
+        const uint32_t y0 = (uint32_t)(q >> 32) ^ x1 ^ key0;
+        const uint32_t y2 = (uint32_t)(p >> 32) ^ x3 ^ key1;
+        x1 = (uint32_t)q;
+        x3 = (uint32_t)p;
+        x0 = y0;
+        x2 = y2;
+        key0 += 0x9E3779B9u;  // Weyl increments: golden ratio, sqrt(3)-1
+        key1 += 0xBB67AE85u;
+    }
+    Words4 o;
+    o.w[0] = x0;
+    o.w[1] = x1;
+    o.w[2] = x2;
+    o.w[3] = x3;
+    return o;
+}
+
+// Exact w mod n for w < 2^32, 1 <= n < 2^31. The binary64 quotient estimate
+// is within 2^-20 of w/n, so the truncated quotient is off by at most one and
+// a single correction step lands in [0, n).
+__device__ __forceinline__ uint32_t mod_exact(uint32_t w, uint32_t n, double inv_n)
+{
+    const uint32_t q = (uint32_t)((double)w * inv_n);
+    int64_t r = (int64_t)w - (int64_t)q * (int64_t)n;
+    r += (r < 0) ? (int64_t)n : 0;
+    r -= (r >= (int64_t)n) ? (int64_t)n : 0;
+    return (uint32_t)r;
+}
+
+// Exact floor division a / b for a, b < 2^32 (same argument as mod_exact).
+__device__ __forceinline__ uint32_t div_exact(uint32_t a, uint32_t b, double inv_b)
+{
+    uint32_t q = (uint32_t)((double)a * inv_b);
+    int64_t r = (int64_t)a - (int64_t)q * (int64_t)b;
+    if (r < 0)
+        q -= 1;
+    else if (r >= (int64_t)b)
+        q += 1;
+    return q;
+}
+
+// ---------------------------------------------------------------------------
+// Cross-lane helpers within a group of G consecutive lanes.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
+
+// Value of `v` held by lane `o` of this lane's group of G lanes. `o` is a
+// compile-time constant after unrolling for G <= 4.
+template <int G>
+__device__ __forceinline__ uint32_t group_bcast(uint32_t v, int o)
+{
+    if constexpr (G == 1) {
+        return v;
+    } else if constexpr (G == 2) {
+        // quad_perm [o, o, 2+o, 2+o]
+        switch (o) {
+        case 0: return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xA0, 0xF, 0xF, false);
+        default: return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xF5, 0xF, 0xF, false);
+        }
+    } else if constexpr (G == 4) {
+        switch (o) {
+        case 0: return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x00, 0xF, 0xF, false);
+        case 1: return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x55, 0xF, 0xF, false);
+        case 2: return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xAA, 0xF, 0xF, false);
+        default: return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xFF, 0xF, 0xF, false);
+        }
+    } else if constexpr (G == 64) {
+        return (uint32_t)__builtin_amdgcn_readlane((int)v, o);
+    } else {
+        const int src = (lane_id() & ~(G - 1)) + o;
+        return (uint32_t)__builtin_amdgcn_ds_bpermute(src << 2, (int)v);
+    }
+}
+
+__device__ __forceinline__ float f_dpp(float v, int ctrl_dummy);
+
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float v)
+{
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+
+__device__ __forceinline__ float xor_f(float v, int mask)
+{
+    const int src = lane_id() ^ mask;
+    return __int_as_float(__builtin_amdgcn_ds_bpermute(src << 2, __float_as_int(v)));
+}
+
+// Sum over the G lanes of a group; every lane of the group receives the
+// same bits (pairings are symmetric and float addition is commutative).
+template <int G>
+__device__ __forceinline__ float group_sum(float v)
+{
+    if constexpr (G >= 64)
+        v += xor_f(v, 32);
+    if constexpr (G >= 32)
+        v += xor_f(v, 16);
+    if constexpr (G >= 16)
+        v += dpp_f<0x140>(v);  // row_mirror: lane l <-> 15-l within 16
+    if constexpr (G >= 8)
+        v += dpp_f<0x141>(v);  // row_half_mirror: lane l <-> 7-l within 8
+    if constexpr (G >= 4)
+        v += dpp_f<0x4E>(v);   // quad_perm [2,3,0,1]
+    if constexpr (G >= 2)
+        v += dpp_f<0xB1>(v);   // quad_perm [1,0,3,2]
+    return v;
+}
+
+// OR of a value over 8 consecutive lanes (lanes 8k..8k+7); all receive it.
+__device__ __forceinline__ uint32_t or8(uint32_t v)
+{
+    v |= (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x141, 0xF, 0xF, false);
+    v |= (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, false);
+    v |= (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, false);
+    return v;
+}
+
+__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
+{
+    for (int off = 32; off > 0; off >>= 1)
+        v += __shfl_xor(v, off);
+    return v;
+}
+
+// ---------------------------------------------------------------------------
+// binary64 squared distance in the defining order: sequential over k,
+// rounded to nearest-even at every step, never fused.
+// ---------------------------------------------------------------------------
+__device__ __noinline__ double sqdist_f64(const float *__restrict__ a, const float *__restrict__ b,
+                                         int d)
+{
+#pragma clang fp contract(off)
+    double acc = 0.0;
+    for (int k = 0; k < d; ++k) {
+        const double delta = (double)a[k] - (double)b[k];
+        const double sq = delta * delta;
+        acc = acc + sq;
+    }
+    return acc;
+}
+
+// ---------------------------------------------------------------------------
+// Lock-free union-find on the label array. Parents always point to smaller
+// indices, so the root of a component is its minimum member.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int32_t ld_relaxed(const int32_t *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void st_relaxed(int32_t *p, int32_t v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Root of x, halving the path on the way (any written value is an ancestor,
+// so concurrent finds and hooks stay consistent).
+__device__ __forceinline__ int32_t uf_find(int32_t *P, int32_t x)
+{
+    int32_t p = ld_relaxed(P + x);
+    while (p != x) {
+        const int32_t gp = ld_relaxed(P + p);
+        if (gp == p)
+            return p;
+        st_relaxed(P + x, gp);
+        x = gp;
+        p = ld_relaxed(P + x);
+    }
+    return x;
+}
+
+// Join the components of a and b: the larger root is hooked under the
+// smaller one by compare-and-swap, retrying from the new roots on conflict.
+__device__ __forceinline__ void uf_unite(int32_t *P, int32_t a, int32_t b)
+{
+    int32_t ra = uf_find(P, a), rb = uf_find(P, b);
+    while (ra != rb) {
+        if (ra > rb) {
+            const int32_t t = ra;
+            ra = rb;
+            rb = t;
+        }
+        const int32_t old = atomicCAS(P + rb, rb, ra);
+        if (old == rb)
+            return;
+        rb = uf_find(P, old);
+        ra = uf_find(P, ra);
+    }
+}
+
+}  // namespace sng

@@ -1,0 +1,220 @@
+// Post-processing of SNG-DBSCAN (Algorithm 1, last three steps) on the
+// device:
+//   core init  core[i] = (int64)deg[i] >= MinPts; the label array becomes the
+//              union-find parent for core points (parent = self) and the
+//              "smallest core neighbour" slot for the others (empty);
+//   hook       every accepted pair is regenerated from its slot bit (Philox
+//              again, no distance work): a core-core pair joins the two
+//              components, a core/non-core pair offers the core index to
+//              the non-core point (atomic min);
+//   finalize   core points take their root (the component's minimum index),
+//              then non-core points take the label of their smallest core
+//              neighbour, or -1.
+// Roots are minimum indices whatever the order of the atomic operations, so
+// the result is deterministic.
+#include "sng_internal.hpp"
+
+namespace sng {
+
+__global__ void k_fill_u32(uint32_t *p, uint64_t count, uint32_t v)
+{
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__global__ void k_fill_u64(unsigned long long *p, uint64_t count, unsigned long long v)
+{
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+static unsigned grid_for(uint64_t items, unsigned block)
+{
+    uint64_t g = (items + block - 1) / block;
+    if (g > 65536ull * 8)
+        g = 65536ull * 8;
+    return (unsigned)(g ? g : 1);
+}
+
+hipError_t launch_fill_u32(uint32_t *p, uint64_t count, uint32_t v, hipStream_t st)
+{
+    if (count == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(count, 256)), dim3(256), 0, st, p, count, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u64(unsigned long long *p, uint64_t count, unsigned long long v,
+                           hipStream_t st)
+{
+    if (count == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(count, 256)), dim3(256), 0, st, p, count, v);
+    return hipGetLastError();
+}
+
+__device__ __forceinline__ void count_add(unsigned long long *cnt, int slot, uint32_t mine)
+{
+    if (!cnt)
+        return;
+    const unsigned long long s = wave_sum_u64(mine);
+    if (lane_id() == 0 && s)
+        atomicAdd(cnt + slot, s);
+}
+
+__global__ __launch_bounds__(256) void k_core_init(Inst I)
+{
+    uint32_t n_core = 0;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < I.n;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        const bool c = (int64_t)I.deg[i] >= (int64_t)I.min_pts;
+        I.core[i] = c;
+        I.labels[i] = c ? (int32_t)i : kNoCore;
+        n_core += c;
+    }
+    count_add(I.cnt, kCntCore, n_core);
+}
+
+__device__ __forceinline__ void hook_pair(const Inst &I, uint32_t a, uint32_t b)
+{
+    const bool ca = I.core[a], cb = I.core[b];
+    if (ca && cb)
+        uf_unite(I.labels, (int32_t)a, (int32_t)b);
+    else if (ca)
+        atomicMin(I.labels + b, (int32_t)a);
+    else if (cb)
+        atomicMin(I.labels + a, (int32_t)b);
+}
+
+// One thread per accept word (eight consecutive calls of the instance).
+__device__ __forceinline__ void hook_word(const Inst &I, uint64_t w)
+{
+    const uint32_t bits = I.mask[I.chunk0 * 8ull + w];
+    if (bits == 0)
+        return;
+    const uint64_t call0 = w * 8ull;
+    uint32_t i = (uint32_t)(call0 / I.C);
+    uint32_t c = (uint32_t)(call0 - (uint64_t)i * I.C);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const uint32_t nib = (bits >> (4 * k)) & 0xFu;
+        if (nib) {
+            const Words4 W = philox10(c, i, I.key0, I.key1);
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+                if (nib & (1u << t))
+                    hook_pair(I, i, mod_exact(W.w[t], I.n, I.inv_n));
+        }
+        if (++c == I.C) {
+            c = 0;
+            ++i;
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_hook_mask(Inst I)
+{
+    const uint64_t words = I.chunks * 8ull;
+    for (uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w < words;
+         w += (uint64_t)gridDim.x * blockDim.x)
+        hook_word(I, w);
+}
+
+__global__ __launch_bounds__(256) void k_hook_edges(Inst I, const int32_t *edges, int64_t n_edges)
+{
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n_edges;
+         e += (int64_t)gridDim.x * blockDim.x)
+        hook_pair(I, (uint32_t)edges[2 * e], (uint32_t)edges[2 * e + 1]);
+}
+
+__global__ __launch_bounds__(256) void k_edge_degrees(const int32_t *edges, int64_t n_edges,
+                                                      uint32_t *deg)
+{
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n_edges;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        atomicAdd(deg + edges[2 * e], 1u);
+        atomicAdd(deg + edges[2 * e + 1], 1u);
+    }
+}
+
+// Core points: label = root of the component (its minimum index).
+__global__ __launch_bounds__(256) void k_compress(Inst I)
+{
+    uint32_t roots = 0;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < I.n;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        if (I.core[i]) {
+            const int32_t r = uf_find(I.labels, (int32_t)i);
+            st_relaxed(I.labels + i, r);
+            roots += (r == (int32_t)i);
+        }
+    }
+    count_add(I.cnt, kCntClusters, roots);
+}
+
+// Non-core points: label of the smallest core neighbour, or noise.
+__global__ __launch_bounds__(256) void k_borders(Inst I)
+{
+    uint32_t noise = 0;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < I.n;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        if (!I.core[i]) {
+            const int32_t b = I.labels[i];
+            const int32_t l = (b == kNoCore) ? -1 : I.labels[b];
+            I.labels[i] = l;
+            noise += (l == -1);
+        }
+    }
+    count_add(I.cnt, kCntNoise, noise);
+}
+
+hipError_t launch_core_init(const Inst &I, hipStream_t st)
+{
+    if (I.n == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_core_init, dim3(grid_for(I.n, 256)), dim3(256), 0, st, I);
+    return hipGetLastError();
+}
+
+hipError_t launch_hook_mask(const Inst &I, hipStream_t st)
+{
+    if (I.chunks == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_hook_mask, dim3(grid_for(I.chunks * 8ull, 256)), dim3(256), 0, st, I);
+    return hipGetLastError();
+}
+
+hipError_t launch_hook_edges(const Inst &I, const int32_t *edges, int64_t n_edges, hipStream_t st)
+{
+    if (n_edges == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_hook_edges, dim3(grid_for((uint64_t)n_edges, 256)), dim3(256), 0, st, I,
+                       edges, n_edges);
+    return hipGetLastError();
+}
+
+hipError_t launch_edge_degrees(const int32_t *edges, int64_t n_edges, uint32_t *deg,
+                               hipStream_t st)
+{
+    if (n_edges == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_edge_degrees, dim3(grid_for((uint64_t)n_edges, 256)), dim3(256), 0, st,
+                       edges, n_edges, deg);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize(const Inst &I, hipStream_t st)
+{
+    if (I.n == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_compress, dim3(grid_for(I.n, 256)), dim3(256), 0, st, I);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(k_borders, dim3(grid_for(I.n, 256)), dim3(256), 0, st, I);
+    return hipGetLastError();
+}
+
+}  // namespace sng

@@ -1,0 +1,46 @@
+// Host-side declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "sng_device.hpp"
+
+namespace sng {
+
+// Launch shape of the sampled-distance pass (resolved from sng_config).
+struct PassAShape {
+    int lanes;            // lanes per pair (G)
+    int chunks_per_wave;  // 64-call chunks per wavefront
+    int stage_lds;        // source row staged in LDS
+    int waves_per_block;
+};
+
+// Fills the binary32 band [lo, hi] around eps2 for dimension d.
+void band_fp32(double eps2, int d, float *lo, float *hi, double *rel);
+
+// Resolves the launch shape for an instance (d, row alignment, user config).
+PassAShape resolve_shape(int d, bool vec_ok, int lanes_req, int cpw_req, int lds_req);
+
+// Sampled-distance pass over `chunks` 64-call chunks of one instance.
+hipError_t launch_pass_a(const Inst &I, const PassAShape &sh, hipStream_t st);
+
+// Sampled-distance pass over every instance of a batch table (device).
+hipError_t launch_pass_a_batch(const Inst *table, int count, const uint64_t *chunk_starts,
+                               uint64_t total_chunks, int d, bool vec_ok, const PassAShape &sh,
+                               hipStream_t st);
+
+// Post-processing kernels (core mask, hooks, finalize).
+hipError_t launch_fill_u32(uint32_t *p, uint64_t count, uint32_t v, hipStream_t st);
+hipError_t launch_fill_u64(unsigned long long *p, uint64_t count, unsigned long long v,
+                           hipStream_t st);
+hipError_t launch_core_init(const Inst &I, hipStream_t st);
+hipError_t launch_hook_mask(const Inst &I, hipStream_t st);
+hipError_t launch_finalize(const Inst &I, hipStream_t st);
+hipError_t launch_edge_degrees(const int32_t *edges, int64_t n_edges, uint32_t *deg,
+                               hipStream_t st);
+hipError_t launch_hook_edges(const Inst &I, const int32_t *edges, int64_t n_edges,
+                             hipStream_t st);
+
+}  // namespace sng

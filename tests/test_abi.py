@@ -1,0 +1,98 @@
+"""The C ABI library loads on the CPU, exports every symbol include/sng.h
+declares, and rejects invalid arguments before touching the device."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2006_06743_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_2006_06743_amd import build
+        build.build()
+    return _lib.load()
+
+
+def header_symbols():
+    src = open(os.path.join(ROOT, "include", "sng.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(sng_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_every_declared_symbol_is_exported(lib):
+    from paper_2006_06743_amd import _lib
+    syms = header_symbols()
+    assert len(syms) >= 15
+    for s in syms:
+        assert hasattr(lib, s), s
+    assert sorted(_lib.EXPORTS) == syms
+
+
+def test_status_strings(lib):
+    for code in range(-6, 1):
+        assert lib.sng_status_string(code)
+    assert lib.sng_status_string(12345) == b"unknown status"
+
+
+def test_samples_per_point(lib):
+    m = ctypes.c_int64()
+    for s, n, want in [(0.01, 10000, 100), (0.001, 10**6, 1000), (0.01, 70000, 700),
+                       (0.002, 500000, 1000), (0.0005, 5 * 10**6, 2500), (0.0, 5, 0),
+                       (1.0, 7, 7), (0.5, 3, 2)]:
+        assert lib.sng_samples_per_point(s, n, ctypes.byref(m)) == 0
+        assert m.value == want
+    assert lib.sng_samples_per_point(-1.0, 5, ctypes.byref(m)) == -1
+    assert lib.sng_samples_per_point(float("nan"), 5, ctypes.byref(m)) == -1
+    assert lib.sng_samples_per_point(float("inf"), 5, ctypes.byref(m)) == -1
+    assert lib.sng_samples_per_point(3.0, 2**31 - 1, ctypes.byref(m)) == -2
+
+
+def test_workspace_sizes(lib):
+    b = ctypes.c_size_t()
+    assert lib.sng_workspace_size(10**6, 16, 1000, 0, ctypes.byref(b)) == 0
+    big = b.value
+    assert big >= 10**6 * 5 + 10**6 * 250 // 8
+    assert lib.sng_workspace_size(10**5, 16, 1000, 0, ctypes.byref(b)) == 0
+    assert b.value < big
+    assert lib.sng_workspace_size(-1, 16, 10, 0, ctypes.byref(b)) == -1
+    assert lib.sng_workspace_size(10, 0, 10, 0, ctypes.byref(b)) == -1
+    assert lib.sng_workspace_size(10, 2, 10, 7, ctypes.byref(b)) == -1
+    assert lib.sng_workspace_size(2**31, 2, 10, 0, ctypes.byref(b)) == -2
+
+
+def test_invalid_arguments_rejected_before_launch(lib):
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
+    ws = ctypes.c_void_p(0x2000)
+    lab = ctypes.c_void_p(0x3000)
+    call = lambda **kw: lib.sng_dbscan(kw.get("X", fake), kw.get("n", 10), kw.get("d", 2),
+                                       kw.get("ld", 2), kw.get("s", 0.5), kw.get("eps", 1.0),
+                                       3, 1, kw.get("labels", lab), None, kw.get("ws", ws),
+                                       kw.get("wsb", 0), None, None)
+    assert call(d=0) == -1
+    assert call(ld=1) == -1
+    assert call(n=-1) == -1
+    assert call(n=2**31) == -2
+    assert call(eps=-0.5) == -1
+    assert call(eps=float("nan")) == -1
+    assert call(eps=float("inf")) == -1
+    assert call(s=-0.1) == -1
+    assert call(s=float("inf")) == -1
+    assert call(s=2**40) == -2
+    assert call(X=None) == -1
+    assert call(X=ctypes.c_void_p(0x1002)) == -1  # not 4-byte aligned
+    assert call(labels=None) == -1
+    assert call(wsb=10) == -3          # workspace too small
+    assert call(ws=None, wsb=10**9) == -3
+    from paper_2006_06743_amd._lib import sng_config
+    bad = sng_config(3, 0, 0, 0)
+    assert lib.sng_dbscan(fake, 10, 2, 2, 0.5, 1.0, 3, 1, lab, None, ws, 10**9,
+                          ctypes.byref(bad), None) == -1
+    assert lib.sng_graph_labels(-1, None, 0, 1, lab, None, ws, 10**9, None) == -1
+    assert lib.sng_graph_labels(5, None, 3, 1, lab, None, ws, 10**9, None) == -1
+    assert lib.sng_graph_labels(5, fake, 3, 1, lab, None, ws, 1, None) == -3

@@ -1,0 +1,192 @@
+"""GPU parity of the plain path (sng_dbscan / sng_degrees / sng_graph_labels)
+against the CPU oracle: degrees and labels must be identical bit for bit."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from paper_2006_06743_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+@pytest.fixture(scope="module")
+def sng():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2006_06743_amd as s
+    s.load()
+    return s
+
+
+def to_gpu(X, pad=0, offset=0):
+    """float32 [n, d] on cuda:0 with row stride d+pad and base offset (floats)."""
+    import torch
+    n, d = X.shape
+    ld = d + pad
+    buf = torch.zeros(offset + max(n, 1) * ld + 4, dtype=torch.float32, device="cuda:0")
+    view = buf[offset:offset + n * ld].view(n, ld)[:, :d] if n > 0 else buf[:0].view(0, d)
+    if n > 0:
+        view.copy_(torch.from_numpy(X))
+    return view
+
+
+def run(sng, X, s, eps, min_pts, seed, cfg=None, pad=0, offset=0):
+    import torch
+    Xg = to_gpu(X, pad, offset)
+    labels, deg, ws = sng.dbscan(Xg, s, eps, min_pts, seed, cfg=cfg)
+    torch.cuda.synchronize()
+    st = sng.stats(ws)
+    return labels.cpu().numpy(), deg.cpu().numpy().view(np.uint32), st
+
+
+def assert_same(got_l, got_d, ref, what):
+    bad_d = np.nonzero(got_d != ref.deg)[0]
+    assert bad_d.size == 0, "%s: %d degrees differ, first at %s" % (what, bad_d.size, bad_d[:5])
+    bad_l = np.nonzero(got_l != ref.labels)[0]
+    assert bad_l.size == 0, "%s: %d labels differ, first at %s" % (what, bad_l.size, bad_l[:5])
+
+
+def test_blobs2d_exact(sng, orc):
+    W = wl.blobs_2d()
+    print("case", W.name, flush=True)
+    gl, gd, st = run(sng, W.X, W.s, W.eps, W.min_pts, W.seed)
+    ref = orc.dbscan(W.X, W.eps, W.min_pts, W.seed, s=W.s)
+    assert_same(gl, gd, ref, W.name)
+    assert st.slots == ref.slots and st.self_pairs == ref.self_pairs
+    assert st.accepted == ref.accepted and st.n_core == ref.n_core
+    assert st.n_clusters == ref.n_clusters and st.n_noise == ref.n_noise
+    assert ref.n_clusters >= 3
+
+
+CASES = []
+_rng = np.random.default_rng(2024)
+for _k in range(40):
+    _n = int(_rng.choice([0, 1, 2, 3, 63, 64, 65, 257, 1000, 3001]))
+    _d = int(_rng.choice([1, 2, 3, 4, 5, 7, 8, 9, 16, 17, 31, 32, 33, 64, 100, 300, 784]))
+    _kind = str(_rng.choice(["blobs", "grid", "uniform", "dupes"]))
+    _s = float(_rng.choice([0.0, 0.003, 0.01, 0.05, 0.3, 1.0]))
+    _pad = int(_rng.choice([0, 0, 1, 3, 4]))
+    _off = int(_rng.choice([0, 0, 1]))
+    CASES.append((_k, _n, _d, _kind, _s, _pad, _off))
+
+
+@pytest.mark.parametrize("case", CASES, ids=["r%d_n%d_d%d_%s_s%g_p%d_o%d" % c for c in CASES])
+def test_random_instances(sng, orc, case):
+    k, n, d, kind, s, pad, off = case
+    rng = np.random.default_rng(5000 + k)
+    X = wl.random_instance(rng, n, d, kind, spread=0.03)
+    seed = int(rng.integers(0, 2**64, dtype=np.uint64))
+    if n >= 2:
+        sample = X[rng.integers(0, n, 64)]
+        dd = np.sqrt(((sample[:, None, :].astype(np.float64) - sample[None]) ** 2).sum(-1))
+        eps = float(np.quantile(dd[dd > 0], rng.uniform(0.01, 0.3))) if np.any(dd > 0) else 1.0
+    else:
+        eps = 0.5
+    print("case", case, "eps", eps, flush=True)
+    for min_pts in [-1, 0, 1, 2, 5]:
+        gl, gd, st = run(sng, X, s, eps, min_pts, seed, pad=pad, offset=off)
+        ref = orc.dbscan(X, eps, min_pts, seed, s=s)
+        assert_same(gl, gd, ref, "%s MinPts=%d" % (case, min_pts))
+        assert st.accepted == ref.accepted
+
+
+@pytest.mark.parametrize("d", [2, 3, 16, 33, 100])
+def test_every_launch_shape_is_identical(sng, orc, d):
+    rng = np.random.default_rng(77 + d)
+    X = wl.random_instance(rng, 2500, d, "blobs", spread=0.02)
+    eps = 0.05 * np.sqrt(d)
+    ref = orc.dbscan(X, eps, 3, 123, s=0.02)
+    vec_pads = [0] if d % 4 == 0 else [0, 4 - d % 4]
+    for lanes in [0, 1, 2, 4, 8, 16, 32, 64]:
+        for cpw in [1, 3, 8, 64]:
+            for lds in [0, 1]:
+                for pad in vec_pads:
+                    cfg = sng.Config(lanes, cpw, lds)
+                    print("shape d=%d lanes=%d cpw=%d lds=%d pad=%d" % (d, lanes, cpw, lds, pad),
+                          flush=True)
+                    gl, gd, _ = run(sng, X, 0.02, eps, 3, 123, cfg=cfg, pad=pad)
+                    assert_same(gl, gd, ref, "d=%d cfg=%s pad=%d" % (d, cfg, pad))
+
+
+def test_degrees_entry_point(sng, orc):
+    import torch
+    W = wl.mixture_16d(sigma=0.25, n_total=50_000)
+    m = orc.samples_per_point(W.s * 20, W.n)
+    deg, ws = sng.degrees(torch.from_numpy(W.X).cuda(), m, W.eps, W.seed)
+    torch.cuda.synchronize()
+    ref, slots, selfp, acc = orc.degrees(W.X, m, W.eps, W.seed)
+    assert np.array_equal(deg.cpu().numpy().view(np.uint32), ref)
+    st = sng.stats(ws)
+    assert st.accepted == acc and st.self_pairs == selfp and st.slots == slots
+
+
+def test_hand_graphs_on_gpu(sng):
+    import torch
+    cases = json.load(open(os.path.join(GOLD, "hand_graphs.json")))["cases"]
+    for c in cases:
+        if c.get("invalid") or c["n"] == 0:
+            continue
+        e = torch.tensor(c["edges"] if c["edges"] else np.zeros((0, 2)), dtype=torch.int32)
+        labels, deg, _ = sng.graph_labels(c["n"], e, c["min_pts"])
+        torch.cuda.synchronize()
+        assert deg.cpu().numpy().tolist() == c["deg"], c["name"]
+        assert labels.cpu().numpy().tolist() == c["labels"], c["name"]
+
+
+def test_edge_cases(sng, orc):
+    cases = [
+        ("n1_all_self", np.zeros((1, 3), np.float32), 1.0, 1e30, 0),
+        ("s0_no_samples", np.random.default_rng(1).normal(size=(50, 4)).astype(np.float32), 0.0, 1.0, 0),
+        ("eps0_duplicates", np.repeat(np.arange(20, dtype=np.float32)[:, None], 3, 1).repeat(5, 0), 0.5, 0.0, 2),
+        ("nan_rows", np.where(np.random.default_rng(2).random((300, 5)) < 0.05, np.nan,
+                              np.random.default_rng(3).random((300, 5))).astype(np.float32), 0.2, 0.6, 2),
+        ("inf_rows", np.where(np.random.default_rng(4).random((300, 2)) < 0.05, np.inf,
+                              np.random.default_rng(5).random((300, 2))).astype(np.float32), 0.2, 0.3, 2),
+        ("huge_eps", np.random.default_rng(6).normal(size=(400, 7)).astype(np.float32) * 1e18, 0.05, 3e38, 3),
+        ("tiny_values", (np.random.default_rng(7).normal(size=(400, 9)) * 1e-30).astype(np.float32), 0.05, 2e-30, 2),
+        ("huge_values", (np.random.default_rng(8).normal(size=(400, 9)) * 1e25).astype(np.float32), 0.05, 3e25, 2),
+    ]
+    for name, X, s, eps, mp in cases:
+        print("edge", name, flush=True)
+        for min_pts in [mp, 0, -3]:
+            gl, gd, _ = run(sng, X, s, eps, min_pts, 99)
+            ref = orc.dbscan(X, eps, min_pts, 99, s=s)
+            assert_same(gl, gd, ref, "%s MinPts=%d" % (name, min_pts))
+
+
+def test_recheck_band_adversarial(sng, orc):
+    """Points on a sphere of radius eps around a centre, and grids whose
+    distances equal eps exactly: many pairs sit within rounding of eps^2, so
+    the binary64 recheck decides them; degrees must still be exact."""
+    rng = np.random.default_rng(9)
+    for d in [2, 3, 16, 33]:
+        u = rng.normal(size=(3000, d))
+        u /= np.linalg.norm(u, axis=1, keepdims=True)
+        eps = 0.37
+        X = np.vstack([np.zeros((1, d)), eps * u]).astype(np.float32)
+        X = np.vstack([X] * 1 + [X[:1]] * 200)  # many copies of the centre
+        gl, gd, st = run(sng, X, 0.5, eps, 3, 4)
+        ref = orc.dbscan(X, eps, 3, 4, s=0.5)
+        assert_same(gl, gd, ref, "sphere d=%d" % d)
+        assert st.rechecked > 0
+        G = rng.integers(0, 4, size=(4000, d)).astype(np.float32)
+        gl, gd, st = run(sng, G, 0.05, 2.0, 4, 5)
+        ref = orc.dbscan(G, 2.0, 4, 5, s=0.05)
+        assert_same(gl, gd, ref, "grid d=%d" % d)
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("sigma", [1.0, 0.25])
+def test_mixture16d_full_size(sng, orc, sigma):
+    """The n=1e6, d=16, s=0.001 workload (1e9 slots) at full size, plus the
+    sigma=0.25 variant whose sampled graph has real clusters."""
+    W = wl.mixture_16d(sigma=sigma)
+    print("case", W.name, flush=True)
+    gl, gd, st = run(sng, W.X, W.s, W.eps, W.min_pts, W.seed)
+    ref = orc.dbscan(W.X, W.eps, W.min_pts, W.seed, s=W.s)
+    assert_same(gl, gd, ref, W.name)
+    assert st.accepted == ref.accepted and st.n_clusters == ref.n_clusters
