@@ -1,0 +1,279 @@
+#!/usr/bin/env python3
+"""SNG-DBSCAN benchmark on one MI355X.
+
+One step is one pass of the whole method (sampled-distance pass, core mask,
+hook, finalize) over the 1e6 x 16 Gaussian-mixture workload (s=0.001,
+eps=2.0, MinPts=5, seed 2) with X already resident in HBM. Prints one JSON
+line with pair evaluations per second (whole job), the roofline of the
+sampled-distance kernel, the oracle's CPU rate on a bounded sample, and the
+plain-vs-mixed / plain-vs-batched comparisons.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-forms] [--no-cpu-baseline]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "sampled pair-distance evals/sec + end-to-end cluster time (plain vs mixed/batched)"
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pass_a_gmm16d_traffic.json")
+PASS_A_SOURCES = ["paper_2006_06743_amd/csrc/sng_pass_a.hip",
+                  "paper_2006_06743_amd/csrc/sng_device.hpp"]
+
+
+def kernel_source_sha() -> str:
+    h = hashlib.sha256()
+    for p in PASS_A_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per launch of the sampled-distance kernel from the committed
+    rocprofv3 counter runs, or None when the kernel changed since."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_sha") != kernel_source_sha():
+        return None
+    return float(t["traffic_bytes_per_launch"])
+
+
+class Timer:
+    def __init__(self, torch):
+        self.torch = torch
+        self.ev = []
+
+    def mark(self):
+        e = self.torch.cuda.Event(enable_timing=True)
+        e.record()
+        self.ev.append(e)
+        return e
+
+
+def cpu_baseline(W, m, budget_s=15.0):
+    """The oracle's sampling step on the first k sources of the workload,
+    k chosen to take about budget_s seconds."""
+    import oracle
+    oracle.load()
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    k0 = min(W.n, 2000)
+    t = time.perf_counter()
+    oracle.degrees(W.X, m, W.eps, W.seed, 0, k0)
+    dt = time.perf_counter() - t
+    k = int(min(W.n, max(k0, k0 * budget_s / max(dt, 1e-3))))
+    t = time.perf_counter()
+    _, slots, _, _ = oracle.degrees(W.X, m, W.eps, W.seed, 0, k)
+    dt = time.perf_counter() - t
+    return {"value": slots / dt, "unit": "pair evals/s", "cores": threads, "kind": "oracle",
+            "sample": "sampling step (Philox partners, binary64 distance, degree "
+                      "accumulation) for sources 0..%d of the same workload: %d slots "
+                      "in %.1f s" % (k - 1, slots, dt)}
+
+
+def time_forms(sng, torch, wl, reps=3):
+    """Plain vs mixed precision (784-d), plain vs one sweep (32-d grid),
+    sequential vs batched instances (64 uneven 3-d instances)."""
+    out = {}
+
+    def cuda_ms(fn, r=reps):
+        fn()
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(r):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / r
+
+    # mixed precision on the 784-d quantised images
+    try:
+        W = wl.mnistlike_784d()
+        X = torch.from_numpy(W.X).cuda()
+        Xlp = torch.from_numpy(W.X_lp.view(__import__("numpy").int16)).cuda()
+        m = sng.samples_per_point(W.s, W.n)
+        lab, deg, ws = sng.dbscan(X, W.s, W.eps, W.min_pts, W.seed)
+        t_plain = cuda_ms(lambda: sng.dbscan(X, W.s, W.eps, W.min_pts, W.seed, labels=lab,
+                                             degrees_out=deg, ws=ws))
+        entry = {"workload": W.name, "slots": W.n * m, "plain_ms": t_plain}
+        try:
+            lab2, deg2, ws2 = sng.dbscan_lowp(X, Xlp, W.s, W.eps, W.min_pts, W.seed)
+            t_mixed = cuda_ms(lambda: sng.dbscan_lowp(X, Xlp, W.s, W.eps, W.min_pts, W.seed,
+                                                      ws=ws2))
+            lab2, deg2, ws2 = sng.dbscan_lowp(X, Xlp, W.s, W.eps, W.min_pts, W.seed, ws=ws2)
+            torch.cuda.synchronize()
+            st = sng.stats(ws2)
+            entry.update({"mixed_bf16_ms": t_mixed, "speedup": t_plain / t_mixed,
+                          "labels_identical": bool(torch.equal(lab, lab2)),
+                          "degrees_identical": bool(torch.equal(deg, deg2)),
+                          "recheck_fraction": st.rechecked / max(1, st.slots),
+                          "band_rel": st.band_rel})
+        except sng.SNGError as e:
+            entry["mixed_bf16"] = "unavailable: %s" % e
+        out["mixed_precision"] = entry
+        del X, Xlp, ws
+    except Exception as e:  # the headline line must still print
+        out["mixed_precision"] = "error: %s" % e
+
+    # one sweep pass versus one plain call per grid point
+    try:
+        W = wl.sweep_32d()
+        X = torch.from_numpy(W.X).cuda()
+        m = sng.samples_per_point(W.s, W.n)
+        entry = {"workload": W.name, "grid": [len(W.eps_grid), len(W.min_pts_grid)],
+                 "slots_per_pass": W.n * m}
+        lab, deg, ws = sng.dbscan(X, W.s, float(W.eps_grid[0]), 2, W.seed)
+        t_one = cuda_ms(lambda: sng.dbscan(X, W.s, float(W.eps_grid[5]), 4, W.seed, labels=lab,
+                                           degrees_out=deg, ws=ws))
+        entry["plain_single_ms"] = t_one
+        entry["plain_all_pairs_ms_est"] = t_one * len(W.eps_grid) * len(W.min_pts_grid)
+        try:
+            sl, sd, sws = sng.sweep(X, W.s, W.eps_grid, W.min_pts_grid, W.seed)
+            t_sweep = cuda_ms(lambda: sng.sweep(X, W.s, W.eps_grid, W.min_pts_grid, W.seed,
+                                                ws=sws), 2)
+            entry.update({"sweep_ms": t_sweep,
+                          "speedup_vs_all_plain": entry["plain_all_pairs_ms_est"] / t_sweep})
+        except sng.SNGError as e:
+            entry["sweep"] = "unavailable: %s" % e
+        out["sweep"] = entry
+        del X, ws
+    except Exception as e:
+        out["sweep"] = "error: %s" % e
+
+    # 64 uneven instances: sequential plain calls versus one batched launch
+    try:
+        B = wl.uneven_batch()
+        Xs = [torch.from_numpy(b.X).cuda() for b in B]
+        slots = sum(b.n * sng.samples_per_point(b.s, b.n) for b in B)
+        wss = [sng.dbscan(x, b.s, b.eps, b.min_pts, b.seed)[2] for x, b in zip(Xs, B)]
+
+        def seq():
+            for x, b, w in zip(Xs, B, wss):
+                sng.dbscan(x, b.s, b.eps, b.min_pts, b.seed, ws=w)
+        entry = {"instances": len(B), "slots": slots, "sequential_ms": cuda_ms(seq)}
+        try:
+            plan = sng.BatchPlan(Xs, [b.s for b in B], [b.eps for b in B],
+                                 [b.min_pts for b in B], [b.seed for b in B])
+            t_graph = cuda_ms(lambda: plan.launch())
+            entry.update({"graph_batch_ms": t_graph, "speedup": entry["sequential_ms"] / t_graph})
+        except sng.SNGError as e:
+            entry["graph_batch"] = "unavailable: %s" % e
+        out["batch"] = entry
+    except Exception as e:
+        out["batch"] = "error: %s" % e
+    torch.cuda.empty_cache()
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-forms", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a 256 MiB device-to-device copy (counter calibration)")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this build runs on one GPU only; --gpus %d (WORLD_SIZE=%d) is not "
+              "supported" % (args.gpus, world), file=sys.stderr, flush=True)
+        sys.exit(2)
+
+    import torch
+    import paper_2006_06743_amd as sng
+    from paper_2006_06743_amd import workloads as wl
+    sng.load()
+
+    W = wl.mixture_16d()
+    m = sng.samples_per_point(W.s, W.n)
+    slots = W.n * m
+    X = torch.from_numpy(W.X).cuda()
+    deg, ws = sng.degrees(X, m, W.eps, W.seed)
+    labels = sng.cluster(X, m, W.eps, W.seed, W.min_pts, deg, ws)
+
+    def step(tm=None):
+        if tm: tm.mark()
+        sng.degrees(X, m, W.eps, W.seed, out=deg, ws=ws)
+        if tm: tm.mark()
+        sng.cluster(X, m, W.eps, W.seed, W.min_pts, deg, ws, labels=labels)
+        if tm: tm.mark()
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    tm = Timer(torch)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(tm)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_per_step = wall * 1e3 / args.steps
+    ev = tm.ev
+    pass_a = [ev[3 * k].elapsed_time(ev[3 * k + 1]) for k in range(args.steps)]
+    post = [ev[3 * k + 1].elapsed_time(ev[3 * k + 2]) for k in range(args.steps)]
+    pass_a_ms = sum(pass_a) / len(pass_a)
+    st = sng.stats(ws)
+
+    alg_bytes = slots * W.d * 4  # one gathered row of X per sample slot
+    achieved = alg_bytes / (pass_a_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
+                "kernel": "k_pass_a (sampled-distance pass)", "algorithmic_bytes": alg_bytes,
+                "avg_launch_ms": pass_a_ms}
+
+    out = {
+        "metric": METRIC,
+        "value": slots / (ms_per_step * 1e-3),
+        "unit": "pair evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": W.name + " (50-component Gaussian mixture + 2% uniform noise)",
+                   "n": W.n, "d": W.d, "s": W.s, "m": m, "eps": W.eps, "min_pts": W.min_pts,
+                   "seed": W.seed, "parallelism": "single GPU"},
+        "end_to_end_ms": ms_per_step,
+        "pass_ms": {"sampled_distance": pass_a_ms, "core_hook_finalize": sum(post) / len(post)},
+        "sampled_distance_evals_per_s": slots / (pass_a_ms * 1e-3),
+        "stats": {"slots": st.slots, "self_pairs": st.self_pairs, "accepted": st.accepted,
+                  "rechecked": st.rechecked, "n_core": st.n_core, "n_clusters": st.n_clusters,
+                  "n_noise": st.n_noise},
+        "roofline": roofline,
+    }
+    del X
+    torch.cuda.empty_cache()
+    if args.calibrate_copy:
+        src = torch.empty(256 << 20, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        out["calibration_copy_bytes"] = src.numel()
+        del src, dst
+    if not args.no_forms:
+        out["forms"] = time_forms(sng, torch, wl)
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(W, m)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -79,7 +79,7 @@ typedef struct {
     int32_t lanes_per_pair;  /* 1,2,4,8,16,32,64 lanes cooperate on one pair */
     int32_t chunks_per_wave; /* 64-call chunks processed by one wavefront */
     int32_t stage_lds;       /* 1: keep the source row in LDS instead of VGPRs */
-    int32_t reserved;
+    int32_t prefetch;        /* partner rows a group gathers ahead: 4, 8 or 16 */
 } sng_config;
 
 /* Device-side counters, copied out by sng_stats_read. */
@@ -112,6 +112,15 @@ int sng_workspace_size(int64_t n, int32_t d, int64_t m, int32_t prec, size_t *by
 int sng_degrees(const float *X, int64_t n, int32_t d, int64_t ld, int64_t m, double eps,
                 uint64_t seed, uint32_t *degrees, void *workspace, size_t ws_bytes,
                 const sng_config *cfg, void *stream);
+
+/* Post-processing (Algorithm 1: core points, components of the core
+ * subgraph, border assignment) continuing from the accept bits that the last
+ * sng_degrees call left in the same workspace (same X, n, d, ld, m, eps and
+ * seed must be passed again). degrees: device u32 [n] as filled by that call.
+ * Several MinPts values may be clustered from one sng_degrees call. */
+int sng_cluster(const float *X, int64_t n, int32_t d, int64_t ld, int64_t m, double eps,
+                uint64_t seed, int32_t min_pts, const uint32_t *degrees, int32_t *labels,
+                void *workspace, size_t ws_bytes, void *stream);
 
 /* Whole method (Algorithm 1): labels[n] (device, i32) receive the cluster
  * labels; degrees (device, u32 [n]) may be NULL. m = ceil(fl64(s*n)). */

@@ -17,7 +17,7 @@ import torch
 from . import _lib
 from ._lib import SNG_BF16, SNG_FP16, SNG_FP32, SNGError, check, sng_config, sng_stats
 
-__all__ = ["dbscan", "dbscan_lowp", "degrees", "graph_labels", "sweep", "batch", "BatchPlan",
+__all__ = ["dbscan", "dbscan_lowp", "degrees", "cluster", "graph_labels", "sweep", "batch", "BatchPlan",
            "samples_per_point", "Config", "Stats", "SNGError", "SNG_FP32", "SNG_BF16",
            "SNG_FP16", "load"]
 
@@ -32,10 +32,11 @@ class Config:
     lanes_per_pair: int = 0
     chunks_per_wave: int = 0
     stage_lds: int = 0
+    prefetch: int = 0
 
     def c(self):
         return ctypes.byref(sng_config(self.lanes_per_pair, self.chunks_per_wave,
-                                       self.stage_lds, 0))
+                                       self.stage_lds, self.prefetch))
 
 
 @dataclass
@@ -105,6 +106,18 @@ def degrees(X: torch.Tensor, m: int, eps: float, seed: int, cfg: Optional[Config
                                   out.data_ptr(), ws.data_ptr(), ws.numel(), _cfg(cfg),
                                   _stream(X)), "sng_degrees")
     return out, ws
+
+
+def cluster(X: torch.Tensor, m: int, eps: float, seed: int, min_pts: int, deg: torch.Tensor,
+            ws: torch.Tensor, labels: Optional[torch.Tensor] = None):
+    """Post-processing continuing from the accept bits a prior degrees() call left in ws."""
+    n, d, ld = _rows(X)
+    if labels is None:
+        labels = torch.empty(n, dtype=torch.int32, device=X.device)
+    check(_lib.load().sng_cluster(X.data_ptr(), n, d, ld, int(m), float(eps), int(seed),
+                                  int(min_pts), deg.data_ptr(), labels.data_ptr(), ws.data_ptr(),
+                                  ws.numel(), _stream(X)), "sng_cluster")
+    return labels
 
 
 def dbscan(X: torch.Tensor, s: float, eps: float, min_pts: int, seed: int,

@@ -18,7 +18,7 @@ SNG_FP32, SNG_BF16, SNG_FP16 = 0, 1, 2
 # Every symbol the header declares (checked by the CPU test suite).
 EXPORTS = [
     "sng_status_string", "sng_samples_per_point", "sng_workspace_size", "sng_degrees",
-    "sng_dbscan", "sng_dbscan_lowp", "sng_graph_workspace_size", "sng_graph_labels",
+    "sng_cluster", "sng_dbscan", "sng_dbscan_lowp", "sng_graph_workspace_size", "sng_graph_labels",
     "sng_sweep_workspace_size", "sng_dbscan_sweep", "sng_batch_workspace_size",
     "sng_dbscan_batch", "sng_batch_plan_create", "sng_batch_plan_launch",
     "sng_batch_plan_destroy", "sng_stats_read",
@@ -27,7 +27,7 @@ EXPORTS = [
 
 class sng_config(ctypes.Structure):
     _fields_ = [("lanes_per_pair", ctypes.c_int32), ("chunks_per_wave", ctypes.c_int32),
-                ("stage_lds", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("stage_lds", ctypes.c_int32), ("prefetch", ctypes.c_int32)]
 
 
 class sng_stats(ctypes.Structure):
@@ -64,6 +64,7 @@ def load() -> ctypes.CDLL:
         "sng_samples_per_point": ([dbl, i64, ctypes.POINTER(i64)], ctypes.c_int),
         "sng_workspace_size": ([i64, i32, i64, i32, ctypes.POINTER(sz)], ctypes.c_int),
         "sng_degrees": ([P, i64, i32, i64, i64, dbl, u64, P, P, sz, cfgp, P], ctypes.c_int),
+        "sng_cluster": ([P, i64, i32, i64, i64, dbl, u64, i32, P, P, P, sz, P], ctypes.c_int),
         "sng_dbscan": ([P, i64, i32, i64, dbl, dbl, i32, u64, P, P, P, sz, cfgp, P],
                        ctypes.c_int),
         "sng_dbscan_lowp": ([P, i64, i32, i64, P, i64, f32, i32, dbl, dbl, i32, u64, P, P, P,

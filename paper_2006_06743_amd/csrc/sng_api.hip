@@ -121,7 +121,8 @@ PassAShape shape_for(const Inst &I, const sng_config *cfg)
 {
     const bool vec_ok = ((uintptr_t)I.X % 16 == 0) && (I.ld % 4 == 0);
     return resolve_shape(I.d, vec_ok, cfg ? cfg->lanes_per_pair : 0,
-                         cfg ? cfg->chunks_per_wave : 0, cfg ? cfg->stage_lds : 0);
+                         cfg ? cfg->chunks_per_wave : 0, cfg ? cfg->stage_lds : 0,
+                         cfg ? cfg->prefetch : 0);
 }
 
 int check_cfg(const sng_config *cfg)
@@ -132,6 +133,8 @@ int check_cfg(const sng_config *cfg)
     if (g != 0 && g != 1 && g != 2 && g != 4 && g != 8 && g != 16 && g != 32 && g != 64)
         return SNG_EINVAL;
     if (cfg->chunks_per_wave < 0 || cfg->chunks_per_wave > 4096)
+        return SNG_EINVAL;
+    if (cfg->prefetch != 0 && cfg->prefetch != 4 && cfg->prefetch != 8 && cfg->prefetch != 16)
         return SNG_EINVAL;
     return SNG_OK;
 }
@@ -232,6 +235,35 @@ int sng_degrees(const float *X, int64_t n, int32_t d, int64_t ld, int64_t m, dou
     I.deg = degrees;
     I.labels = nullptr;
     return run_plain(I, cfg, false, st);
+}
+
+int sng_cluster(const float *X, int64_t n, int32_t d, int64_t ld, int64_t m, double eps,
+                uint64_t seed, int32_t min_pts, const uint32_t *degrees, int32_t *labels,
+                void *workspace, size_t ws_bytes, void *stream)
+{
+    int rc = check_points(X, n, d, ld);
+    if (rc) return rc;
+    if ((rc = check_eps(eps))) return rc;
+    if (m < 0) return SNG_EINVAL;
+    if (m > kMaxM) return SNG_ERANGE;
+    if (n > 0 && (!degrees || !labels)) return SNG_EINVAL;
+    const size_t need = plain_ws_bytes(n, m);
+    if (!workspace || ws_bytes < need) return SNG_EWORKSPACE;
+    hipStream_t st = (hipStream_t)stream;
+    Carve cv(workspace);
+    Inst I = make_inst(X, n, d, ld, m, eps, seed, min_pts);
+    I.cnt = cv.take<unsigned long long>(kHeaderBytes / 8);
+    (void)cv.take<uint32_t>((size_t)n);
+    I.core = cv.take<uint8_t>((size_t)n);
+    I.mask = cv.take<uint32_t>(sizes_for(n, m).chunks * 8);
+    I.deg = const_cast<uint32_t *>(degrees);  // read only below
+    I.labels = labels;
+    SNG_TRY(launch_fill_u64(I.cnt + kCntCore, 3, 0ull, st));  // core/cluster/noise counts
+    SNG_TRY(launch_core_init(I, st));
+    if (I.m > 0)
+        SNG_TRY(launch_hook_mask(I, st));
+    SNG_TRY(launch_finalize(I, st));
+    return SNG_OK;
 }
 
 int sng_dbscan(const float *X, int64_t n, int32_t d, int64_t ld, double s, double eps,

@@ -15,13 +15,15 @@ struct PassAShape {
     int chunks_per_wave;  // 64-call chunks per wavefront
     int stage_lds;        // source row staged in LDS
     int waves_per_block;
+    int owners_per_batch; // Philox calls of a group whose partners are fetched together
 };
 
 // Fills the binary32 band [lo, hi] around eps2 for dimension d.
 void band_fp32(double eps2, int d, float *lo, float *hi, double *rel);
 
 // Resolves the launch shape for an instance (d, row alignment, user config).
-PassAShape resolve_shape(int d, bool vec_ok, int lanes_req, int cpw_req, int lds_req);
+PassAShape resolve_shape(int d, bool vec_ok, int lanes_req, int cpw_req, int lds_req,
+                         int prefetch_req);
 
 // Sampled-distance pass over `chunks` 64-call chunks of one instance.
 hipError_t launch_pass_a(const Inst &I, const PassAShape &sh, hipStream_t st);

@@ -24,27 +24,39 @@
 namespace sng {
 
 // ---------------------------------------------------------------------------
-// Source-row policies: how a group holds x_i and forms its partial sum of
-// squared differences against a gathered row x_j.
+// Row policies: how a group holds x_i, fetches its share of a gathered row x_j
+// into registers (fetch), and forms its partial sum of squared differences
+// (partial). Fetch and partial are split so that a batch of partner rows can
+// be in flight before the first distance is formed.
 // ---------------------------------------------------------------------------
 
 // G = 1, compile-time dimension D <= 8, scalar loads (any row stride).
 template <int D>
 struct SmallRow {
     static constexpr int kG = 1;
-    float r[D];
-    __device__ __forceinline__ void load(const float *row, int, int, float *)
+    static constexpr bool kPrefetch = true;
+    struct Buf {
+        float v[D];
+    };
+    Buf r;
+    __device__ __forceinline__ static Buf fetch(const float *__restrict__ row, int, int)
     {
+        Buf b;
 #pragma unroll
         for (int k = 0; k < D; ++k)
-            r[k] = row[k];
+            b.v[k] = row[k];
+        return b;
     }
-    __device__ __forceinline__ float partial(const float *__restrict__ row, int, int) const
+    __device__ __forceinline__ void load(const float *row, int q, int d, float *)
+    {
+        r = fetch(row, q, d);
+    }
+    __device__ __forceinline__ float partial(const Buf &b, int, int) const
     {
         float acc = 0.0f;
 #pragma unroll
         for (int k = 0; k < D; ++k) {
-            const float e = r[k] - row[k];
+            const float e = r.v[k] - b.v[k];
             acc = __builtin_fmaf(e, e, acc);
         }
         return acc;
@@ -56,35 +68,42 @@ struct SmallRow {
 template <int G, int NV, bool FULL>
 struct VecRow {
     static constexpr int kG = G;
-    float4 r[NV];
-    __device__ __forceinline__ void load(const float *row, int q, int d, float *)
+    static constexpr bool kPrefetch = true;
+    struct Buf {
+        float4 v[NV];
+    };
+    Buf r;
+    __device__ __forceinline__ static Buf fetch(const float *__restrict__ row, int q, int d)
     {
+        Buf b;
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
             const int k = 4 * (v * G + q);
             if (FULL || k < d)
-                r[v] = *reinterpret_cast<const float4 *>(row + k);
+                b.v[v] = *reinterpret_cast<const float4 *>(row + k);
             else
-                r[v] = make_float4(0.f, 0.f, 0.f, 0.f);
+                b.v[v] = make_float4(0.f, 0.f, 0.f, 0.f);
         }
+        return b;
     }
-    __device__ __forceinline__ float partial(const float *__restrict__ row, int q, int d) const
+    __device__ __forceinline__ void load(const float *row, int q, int d, float *)
+    {
+        r = fetch(row, q, d);
+    }
+    __device__ __forceinline__ float partial(const Buf &b, int q, int d) const
     {
         float acc = 0.0f;
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
             const int k = 4 * (v * G + q);
-            if (FULL || k < d) {
-                const float4 b = *reinterpret_cast<const float4 *>(row + k);
-                const float e0 = r[v].x - b.x;
-                const float e1 = (FULL || k + 1 < d) ? r[v].y - b.y : 0.0f;
-                const float e2 = (FULL || k + 2 < d) ? r[v].z - b.z : 0.0f;
-                const float e3 = (FULL || k + 3 < d) ? r[v].w - b.w : 0.0f;
-                acc = __builtin_fmaf(e0, e0, acc);
-                acc = __builtin_fmaf(e1, e1, acc);
-                acc = __builtin_fmaf(e2, e2, acc);
-                acc = __builtin_fmaf(e3, e3, acc);
-            }
+            const float e0 = r.v[v].x - b.v[v].x;
+            const float e1 = (FULL || k + 1 < d) ? r.v[v].y - b.v[v].y : 0.0f;
+            const float e2 = (FULL || k + 2 < d) ? r.v[v].z - b.v[v].z : 0.0f;
+            const float e3 = (FULL || k + 3 < d) ? r.v[v].w - b.v[v].w : 0.0f;
+            acc = __builtin_fmaf(e0, e0, acc);
+            acc = __builtin_fmaf(e1, e1, acc);
+            acc = __builtin_fmaf(e2, e2, acc);
+            acc = __builtin_fmaf(e3, e3, acc);
         }
         return acc;
     }
@@ -95,34 +114,47 @@ struct VecRow {
 template <int G, int NS>
 struct ScalarRow {
     static constexpr int kG = G;
-    float r[NS];
-    __device__ __forceinline__ void load(const float *row, int q, int d, float *)
+    static constexpr bool kPrefetch = true;
+    struct Buf {
+        float v[NS];
+    };
+    Buf r;
+    __device__ __forceinline__ static Buf fetch(const float *__restrict__ row, int q, int d)
     {
+        Buf b;
 #pragma unroll
         for (int v = 0; v < NS; ++v) {
             const int k = v * G + q;
-            r[v] = (k < d) ? row[k] : 0.0f;
+            b.v[v] = (k < d) ? row[k] : 0.0f;
         }
+        return b;
     }
-    __device__ __forceinline__ float partial(const float *__restrict__ row, int q, int d) const
+    __device__ __forceinline__ void load(const float *row, int q, int d, float *)
+    {
+        r = fetch(row, q, d);
+    }
+    __device__ __forceinline__ float partial(const Buf &b, int, int) const
     {
         float acc = 0.0f;
 #pragma unroll
         for (int v = 0; v < NS; ++v) {
-            const int k = v * G + q;
-            if (k < d) {
-                const float e = r[v] - row[k];
-                acc = __builtin_fmaf(e, e, acc);
-            }
+            const float e = r.v[v] - b.v[v];
+            acc = __builtin_fmaf(e, e, acc);
         }
         return acc;
     }
 };
 
-// G = 64: the source row is staged in this wave's LDS slice (any d that fits).
+// G = 64: the source row is staged in this wave's LDS slice (any d that fits);
+// the partner row is streamed from memory while the distance is formed.
 struct LdsRow {
     static constexpr int kG = 64;
+    static constexpr bool kPrefetch = false;
+    struct Buf {
+        const float *p;
+    };
     float *s = nullptr;
+    __device__ __forceinline__ static Buf fetch(const float *row, int, int) { return Buf{row}; }
     __device__ __forceinline__ void load(const float *row, int q, int d, float *slice)
     {
         s = slice;
@@ -133,11 +165,11 @@ struct LdsRow {
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
-    __device__ __forceinline__ float partial(const float *__restrict__ row, int q, int d) const
+    __device__ __forceinline__ float partial(const Buf &b, int q, int d) const
     {
         float acc = 0.0f;
         for (int k = q; k < d; k += 64) {
-            const float e = s[k] - row[k];
+            const float e = s[k] - b.p[k];
             acc = __builtin_fmaf(e, e, acc);
         }
         return acc;
@@ -166,12 +198,15 @@ __device__ __forceinline__ void flush_source(GroupState<Row> &gs, uint32_t *deg,
     gs.deg_i = 0;
 }
 
-// Processes local chunks [ch_lo, ch_hi) of instance I.
-template <class Row>
+// Processes local chunks [ch_lo, ch_hi) of instance I. OB owners (calls) of
+// a group are handled per batch: their 4*OB partner rows are fetched first,
+// then decided one after another.
+template <class Row, int OB>
 __device__ __forceinline__ void pass_a_range(const Inst &I, uint64_t ch_lo, uint64_t ch_hi,
                                              float *slice, Tally &tally)
 {
     constexpr int G = Row::kG;
+    static_assert(OB >= 1 && OB <= G, "owners per batch");
     const int lane = lane_id();
     const int q = lane & (G - 1);
     const float *__restrict__ X = I.X;
@@ -200,46 +235,75 @@ __device__ __forceinline__ void pass_a_range(const Inst &I, uint64_t ch_lo, uint
             j[w] = mod_exact(W.w[w], I.n, I.inv_n);
 
         uint32_t nib = 0;  // accept bits of this lane's own call
-        constexpr int kOwnerUnroll = (G <= 4) ? G : 1;
-#pragma unroll kOwnerUnroll
-        for (int o = 0; o < G; ++o) {
-            const uint32_t io = group_bcast<G>(ii, o);
-            const uint32_t nv = group_bcast<G>(nvalid, o);
+        constexpr int kBatches = G / OB;
+        constexpr int kBatchUnroll = (G <= 4) ? kBatches : 1;
+#pragma unroll kBatchUnroll
+        for (int ob = 0; ob < kBatches; ++ob) {
+            uint32_t io[OB], nv[OB], jj[OB][4];
+            typename Row::Buf buf[OB][4];
 #pragma unroll
-            for (int w = 0; w < 4; ++w) {
-                const uint32_t jj = group_bcast<G>(j[w], o);
-                if ((uint32_t)w >= nv)
-                    continue;  // slot beyond m, or call beyond n (group-uniform)
-                if (jj == io) {
-                    tally.self += (q == 0);
-                    continue;
-                }
-                if (io != gs.cached) {
-                    flush_source(gs, I.deg, q);
-                    gs.xi.load(X + (int64_t)io * ld, q, d, slice);
-                    gs.cached = io;
-                }
-                const float *rowj = X + (int64_t)jj * ld;
-                float F = group_sum<G>(gs.xi.partial(rowj, q, d));
-                F = __int_as_float((int)group_bcast<G>((uint32_t)__float_as_int(F), 0));
-                bool acc;
-                if (F <= I.lo) {
-                    acc = true;
-                } else if (F > I.hi) {
-                    acc = false;
-                } else {
-                    const double D = sqdist_f64(X + (int64_t)io * ld, rowj, d);
-                    acc = (D <= I.eps2);
-                    tally.rechecked += (q == 0);
-                }
-                if (acc) {
-                    gs.deg_i += 1;
-                    if (q == 0) {
-                        atomicAdd(I.deg + jj, 1u);
-                        tally.accepted += 1;
+            for (int b = 0; b < OB; ++b) {
+                const int o = ob * OB + b;
+                io[b] = group_bcast<G>(ii, o);
+                nv[b] = group_bcast<G>(nvalid, o);
+#pragma unroll
+                for (int w = 0; w < 4; ++w)
+                    jj[b][w] = group_bcast<G>(j[w], o);
+            }
+            if constexpr (Row::kPrefetch) {
+                // Issue every partner gather of the batch before using any.
+#pragma unroll
+                for (int b = 0; b < OB; ++b)
+#pragma unroll
+                    for (int w = 0; w < 4; ++w) {
+                        const bool live = (uint32_t)w < nv[b] && jj[b][w] != io[b];
+                        const uint32_t src = live ? jj[b][w] : 0u;  // row 0 always exists
+                        buf[b][w] = Row::fetch(X + (int64_t)src * ld, q, d);
                     }
-                    if (q == o)
-                        nib |= 1u << w;
+            }
+#pragma unroll
+            for (int b = 0; b < OB; ++b) {
+                const int o = ob * OB + b;
+                if (nv[b] == 0)
+                    continue;  // call beyond n (group-uniform)
+                if (io[b] != gs.cached) {
+                    flush_source(gs, I.deg, q);
+                    gs.xi.load(X + (int64_t)io[b] * ld, q, d, slice);
+                    gs.cached = io[b];
+                }
+#pragma unroll
+                for (int w = 0; w < 4; ++w) {
+                    if ((uint32_t)w >= nv[b])
+                        continue;  // slot beyond m (group-uniform)
+                    const uint32_t jw = jj[b][w];
+                    if (jw == io[b]) {
+                        tally.self += (q == 0);
+                        continue;
+                    }
+                    const float *rowj = X + (int64_t)jw * ld;
+                    if constexpr (!Row::kPrefetch)
+                        buf[b][w] = Row::fetch(rowj, q, d);
+                    float F = group_sum<G>(gs.xi.partial(buf[b][w], q, d));
+                    F = __int_as_float((int)group_bcast<G>((uint32_t)__float_as_int(F), 0));
+                    bool acc;
+                    if (F <= I.lo) {
+                        acc = true;
+                    } else if (F > I.hi) {
+                        acc = false;
+                    } else {
+                        const double D = sqdist_f64(X + (int64_t)io[b] * ld, rowj, d);
+                        acc = (D <= I.eps2);
+                        tally.rechecked += (q == 0);
+                    }
+                    if (acc) {
+                        gs.deg_i += 1;
+                        if (q == 0) {
+                            atomicAdd(I.deg + jw, 1u);
+                            tally.accepted += 1;
+                        }
+                        if (q == o)
+                            nib |= 1u << w;
+                    }
                 }
             }
         }
@@ -273,7 +337,7 @@ __device__ __forceinline__ void commit_tally(const Tally &t, unsigned long long 
     }
 }
 
-template <class Row>
+template <class Row, int OB>
 __global__ __launch_bounds__(256) void k_pass_a(Inst I, uint32_t cpw, uint32_t slice_floats)
 {
     extern __shared__ float lds[];
@@ -284,13 +348,13 @@ __global__ __launch_bounds__(256) void k_pass_a(Inst I, uint32_t cpw, uint32_t s
     const uint64_t hi = min(lo + cpw, I.chunks);
     float *slice = lds + (threadIdx.x / kWave) * slice_floats;
     Tally t;
-    pass_a_range<Row>(I, lo, hi, slice, t);
+    pass_a_range<Row, OB>(I, lo, hi, slice, t);
     commit_tally(t, I.cnt);
 }
 
 // Batch form: global chunks are split at instance boundaries (each instance
 // starts on a chunk of its own), so a wave looks its instance up per chunk.
-template <class Row>
+template <class Row, int OB>
 __global__ __launch_bounds__(256) void k_pass_a_batch(const Inst *__restrict__ table, int count,
                                                       const uint64_t *__restrict__ starts,
                                                       uint64_t total, uint32_t cpw,
@@ -316,7 +380,7 @@ __global__ __launch_bounds__(256) void k_pass_a_batch(const Inst *__restrict__ t
         const Inst I = table[a];
         const uint64_t end = min(hi, starts[a + 1]);
         Tally t;
-        pass_a_range<Row>(I, lo - starts[a], end - starts[a], slice, t);
+        pass_a_range<Row, OB>(I, lo - starts[a], end - starts[a], slice, t);
         commit_tally(t, I.cnt);
         lo = end;
     }
@@ -364,7 +428,8 @@ void band_fp32(double eps2, int d, float *lo, float *hi, double *rel)
         *rel = a + c;
 }
 
-PassAShape resolve_shape(int d, bool vec_ok, int lanes_req, int cpw_req, int lds_req)
+PassAShape resolve_shape(int d, bool vec_ok, int lanes_req, int cpw_req, int lds_req,
+                         int prefetch_req)
 {
     PassAShape s;
     s.waves_per_block = 4;
@@ -384,12 +449,17 @@ PassAShape resolve_shape(int d, bool vec_ok, int lanes_req, int cpw_req, int lds
     }
     s.lanes = g;
     s.chunks_per_wave = cpw_req > 0 ? cpw_req : 8;
+    int ob = prefetch_req > 0 ? prefetch_req / 4 : (g >= 2 ? 2 : 1);
+    ob = ob >= 4 ? 4 : (ob >= 2 ? 2 : 1);
+    while (ob > g)
+        ob >>= 1;
+    s.owners_per_batch = ob;
     return s;
 }
 
 namespace {
 
-template <class Row>
+template <class Row, int OB>
 hipError_t go(const Inst &I, const PassAShape &sh, uint32_t slice, hipStream_t st)
 {
     const uint64_t waves = (I.chunks + sh.chunks_per_wave - 1) / sh.chunks_per_wave;
@@ -399,12 +469,12 @@ hipError_t go(const Inst &I, const PassAShape &sh, uint32_t slice, hipStream_t s
     if (blocks > 0x7FFFFFFFull)
         return hipErrorInvalidValue;
     const size_t lds = (size_t)slice * sizeof(float) * sh.waves_per_block;
-    hipLaunchKernelGGL(k_pass_a<Row>, dim3((unsigned)blocks), dim3(64 * sh.waves_per_block), lds,
-                       st, I, (uint32_t)sh.chunks_per_wave, slice);
+    hipLaunchKernelGGL((k_pass_a<Row, OB>), dim3((unsigned)blocks), dim3(64 * sh.waves_per_block),
+                       lds, st, I, (uint32_t)sh.chunks_per_wave, slice);
     return hipGetLastError();
 }
 
-template <class Row>
+template <class Row, int OB>
 hipError_t go_batch(const Inst *table, int count, const uint64_t *starts, uint64_t total,
                     const PassAShape &sh, uint32_t slice, hipStream_t st)
 {
@@ -412,43 +482,62 @@ hipError_t go_batch(const Inst *table, int count, const uint64_t *starts, uint64
     const uint64_t blocks = (waves + sh.waves_per_block - 1) / sh.waves_per_block;
     if (blocks == 0)
         return hipSuccess;
+    if (blocks > 0x7FFFFFFFull)
+        return hipErrorInvalidValue;
     const size_t lds = (size_t)slice * sizeof(float) * sh.waves_per_block;
-    hipLaunchKernelGGL(k_pass_a_batch<Row>, dim3((unsigned)blocks), dim3(64 * sh.waves_per_block),
-                       lds, st, table, count, starts, total, (uint32_t)sh.chunks_per_wave, slice);
+    hipLaunchKernelGGL((k_pass_a_batch<Row, OB>), dim3((unsigned)blocks),
+                       dim3(64 * sh.waves_per_block), lds, st, table, count, starts, total,
+                       (uint32_t)sh.chunks_per_wave, slice);
     return hipGetLastError();
 }
 
-// Calls F.template operator()<Row>() with the row policy for (d, shape).
+// Calls fn.template operator()<Row, OB>(slice) for the policy of (d, shape).
+template <class Row, class Fn>
+hipError_t with_ob(const PassAShape &sh, uint32_t slice, Fn &&fn)
+{
+    constexpr int G = Row::kG;
+    if constexpr (G >= 4) {
+        if (sh.owners_per_batch >= 4)
+            return fn.template operator()<Row, 4>(slice);
+    }
+    if constexpr (G >= 2) {
+        if (sh.owners_per_batch >= 2)
+            return fn.template operator()<Row, 2>(slice);
+    }
+    return fn.template operator()<Row, 1>(slice);
+}
+
 template <class Fn>
 hipError_t dispatch(int d, bool vec_ok, const PassAShape &sh, Fn &&fn)
 {
     const int G = sh.lanes;
+    const uint32_t lds_slice = (uint32_t)((d + 63) & ~63);
     if (sh.stage_lds)
-        return fn.template operator()<LdsRow>((uint32_t)((d + 63) & ~63));
+        return fn.template operator()<LdsRow, 1>(lds_slice);
     if (d <= 8 && G == 1) {
         switch (d) {
-        case 1: return fn.template operator()<SmallRow<1>>(0u);
-        case 2: return fn.template operator()<SmallRow<2>>(0u);
-        case 3: return fn.template operator()<SmallRow<3>>(0u);
-        case 4: return fn.template operator()<SmallRow<4>>(0u);
-        case 5: return fn.template operator()<SmallRow<5>>(0u);
-        case 6: return fn.template operator()<SmallRow<6>>(0u);
-        case 7: return fn.template operator()<SmallRow<7>>(0u);
-        default: return fn.template operator()<SmallRow<8>>(0u);
+        case 1: return fn.template operator()<SmallRow<1>, 1>(0u);
+        case 2: return fn.template operator()<SmallRow<2>, 1>(0u);
+        case 3: return fn.template operator()<SmallRow<3>, 1>(0u);
+        case 4: return fn.template operator()<SmallRow<4>, 1>(0u);
+        case 5: return fn.template operator()<SmallRow<5>, 1>(0u);
+        case 6: return fn.template operator()<SmallRow<6>, 1>(0u);
+        case 7: return fn.template operator()<SmallRow<7>, 1>(0u);
+        default: return fn.template operator()<SmallRow<8>, 1>(0u);
         }
     }
     if (vec_ok) {
         const int units = (d + 3) / 4;
         const int nv = (units + G - 1) / G;
         const bool full = (d == 4 * G * nv);
-#define SNG_VEC(GG)                                                                     \
-    if (G == GG) {                                                                      \
-        if (nv == 1) return full ? fn.template operator()<VecRow<GG, 1, true>>(0u)      \
-                                 : fn.template operator()<VecRow<GG, 1, false>>(0u);    \
-        if (nv == 2) return full ? fn.template operator()<VecRow<GG, 2, true>>(0u)      \
-                                 : fn.template operator()<VecRow<GG, 2, false>>(0u);    \
-        if (nv <= 4) return fn.template operator()<VecRow<GG, 4, false>>(0u);           \
-        if (nv <= 8) return fn.template operator()<VecRow<GG, 8, false>>(0u);           \
+#define SNG_VEC(GG)                                                                          \
+    if (G == GG) {                                                                           \
+        if (nv == 1)                                                                         \
+            return full ? with_ob<VecRow<GG, 1, true>>(sh, 0u, fn)                           \
+                        : with_ob<VecRow<GG, 1, false>>(sh, 0u, fn);                         \
+        if (nv == 2) return with_ob<VecRow<GG, 2, false>>(sh, 0u, fn);                       \
+        if (nv <= 4) return fn.template operator()<VecRow<GG, 4, false>, 1>(0u);             \
+        if (nv <= 8) return fn.template operator()<VecRow<GG, 8, false>, 1>(0u);             \
     }
         SNG_VEC(1)
         SNG_VEC(2)
@@ -460,13 +549,13 @@ hipError_t dispatch(int d, bool vec_ok, const PassAShape &sh, Fn &&fn)
 #undef SNG_VEC
     } else {
         const int ns = (d + G - 1) / G;
-#define SNG_SCA(GG)                                                                     \
-    if (G == GG) {                                                                      \
-        if (ns <= 1) return fn.template operator()<ScalarRow<GG, 1>>(0u);               \
-        if (ns <= 2) return fn.template operator()<ScalarRow<GG, 2>>(0u);               \
-        if (ns <= 4) return fn.template operator()<ScalarRow<GG, 4>>(0u);               \
-        if (ns <= 8) return fn.template operator()<ScalarRow<GG, 8>>(0u);               \
-        if (ns <= 16) return fn.template operator()<ScalarRow<GG, 16>>(0u);             \
+#define SNG_SCA(GG)                                                                          \
+    if (G == GG) {                                                                           \
+        if (ns <= 1) return fn.template operator()<ScalarRow<GG, 1>, 1>(0u);                 \
+        if (ns <= 2) return fn.template operator()<ScalarRow<GG, 2>, 1>(0u);                 \
+        if (ns <= 4) return fn.template operator()<ScalarRow<GG, 4>, 1>(0u);                 \
+        if (ns <= 8) return fn.template operator()<ScalarRow<GG, 8>, 1>(0u);                 \
+        if (ns <= 16) return fn.template operator()<ScalarRow<GG, 16>, 1>(0u);               \
     }
         SNG_SCA(4)
         SNG_SCA(16)
@@ -474,7 +563,7 @@ hipError_t dispatch(int d, bool vec_ok, const PassAShape &sh, Fn &&fn)
 #undef SNG_SCA
     }
     // anything else: LDS-staged wave-per-pair
-    return fn.template operator()<LdsRow>((uint32_t)((d + 63) & ~63));
+    return fn.template operator()<LdsRow, 1>(lds_slice);
 }
 
 }  // namespace
@@ -484,8 +573,11 @@ hipError_t launch_pass_a(const Inst &I, const PassAShape &sh, hipStream_t st)
     if (I.chunks == 0)
         return hipSuccess;
     const bool vec_ok = ((uintptr_t)I.X % 16 == 0) && (I.ld % 4 == 0);
-    return dispatch(I.d, vec_ok, sh, [&]<class Row>(uint32_t slice) {
-        return go<Row>(I, sh, slice, st);
+    if ((size_t)((I.d + 63) & ~63) * 4 * sh.waves_per_block > 65536 &&
+        (sh.stage_lds || (!vec_ok && I.d > 16 * 64) || (vec_ok && I.d > 4 * 8 * 64)))
+        return hipErrorInvalidValue;
+    return dispatch(I.d, vec_ok, sh, [&]<class Row, int OB>(uint32_t slice) {
+        return go<Row, OB>(I, sh, slice, st);
     });
 }
 
@@ -495,8 +587,8 @@ hipError_t launch_pass_a_batch(const Inst *table, int count, const uint64_t *sta
 {
     if (total == 0)
         return hipSuccess;
-    return dispatch(d, vec_ok, sh, [&]<class Row>(uint32_t slice) {
-        return go_batch<Row>(table, count, starts, total, sh, slice, st);
+    return dispatch(d, vec_ok, sh, [&]<class Row, int OB>(uint32_t slice) {
+        return go_batch<Row, OB>(table, count, starts, total, sh, slice, st);
     });
 }
 

@@ -101,15 +101,15 @@ def test_every_launch_shape_is_identical(sng, orc, d):
     eps = 0.05 * np.sqrt(d)
     ref = orc.dbscan(X, eps, 3, 123, s=0.02)
     vec_pads = [0] if d % 4 == 0 else [0, 4 - d % 4]
-    for lanes in [0, 1, 2, 4, 8, 16, 32, 64]:
-        for cpw in [1, 3, 8, 64]:
-            for lds in [0, 1]:
-                for pad in vec_pads:
-                    cfg = sng.Config(lanes, cpw, lds)
-                    print("shape d=%d lanes=%d cpw=%d lds=%d pad=%d" % (d, lanes, cpw, lds, pad),
-                          flush=True)
-                    gl, gd, _ = run(sng, X, 0.02, eps, 3, 123, cfg=cfg, pad=pad)
-                    assert_same(gl, gd, ref, "d=%d cfg=%s pad=%d" % (d, cfg, pad))
+    shapes = [(lanes, cpw, lds, pf) for lanes in [0, 1, 2, 4, 8, 16, 32, 64]
+              for cpw in [1, 3, 64] for lds in [0, 1] for pf in [0, 4, 8, 16]
+              if not (lds and pf)]
+    for lanes, cpw, lds, pf in shapes:
+        for pad in vec_pads:
+            cfg = sng.Config(lanes, cpw, lds, pf)
+            print("shape d=%d cfg=%s pad=%d" % (d, cfg, pad), flush=True)
+            gl, gd, _ = run(sng, X, 0.02, eps, 3, 123, cfg=cfg, pad=pad)
+            assert_same(gl, gd, ref, "d=%d cfg=%s pad=%d" % (d, cfg, pad))
 
 
 def test_degrees_entry_point(sng, orc):
@@ -190,3 +190,19 @@ def test_mixture16d_full_size(sng, orc, sigma):
     ref = orc.dbscan(W.X, W.eps, W.min_pts, W.seed, s=W.s)
     assert_same(gl, gd, ref, W.name)
     assert st.accepted == ref.accepted and st.n_clusters == ref.n_clusters
+
+
+def test_cluster_entry_point_many_minpts(sng, orc):
+    """One sampled-distance pass, then post-processing for several MinPts."""
+    import torch
+    W = wl.mixture_16d(sigma=0.25, n_total=60_000)
+    m = orc.samples_per_point(0.02, W.n)
+    X = torch.from_numpy(W.X).cuda()
+    deg, ws = sng.degrees(X, m, W.eps, W.seed)
+    for mp in [-1, 1, 3, 5, 12, 40]:
+        lab = sng.cluster(X, m, W.eps, W.seed, mp, deg, ws)
+        torch.cuda.synchronize()
+        ref = orc.dbscan(W.X, W.eps, mp, W.seed, m=m)
+        assert_same(lab.cpu().numpy(), deg.cpu().numpy().view(np.uint32), ref, "MinPts=%d" % mp)
+        st = sng.stats(ws)
+        assert st.n_core == ref.n_core and st.n_clusters == ref.n_clusters
