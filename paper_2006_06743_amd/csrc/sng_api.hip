@@ -82,6 +82,16 @@ size_t plain_ws_bytes(int64_t n, int64_t m)
     return b;
 }
 
+// The mixed-precision pass adds per-row statistics and a queue of undecided
+// slots large enough for every slot, so it can never overflow.
+size_t lowp_ws_bytes(int64_t n, int64_t m)
+{
+    size_t b = plain_ws_bytes(n, m);
+    b = align_up(b + (size_t)n * 4 * sizeof(double));
+    b = align_up(b + (size_t)n * (size_t)m * sizeof(uint64_t));
+    return b;
+}
+
 inline int hip_rc(hipError_t e) { return e == hipSuccess ? SNG_OK : SNG_EHIP; }
 
 #define SNG_TRY(expr)                       \
@@ -208,7 +218,7 @@ int sng_workspace_size(int64_t n, int32_t d, int64_t m, int32_t prec, size_t *by
         return SNG_ERANGE;
     if (prec != SNG_FP32 && prec != SNG_BF16 && prec != SNG_FP16)
         return SNG_EINVAL;
-    *bytes = plain_ws_bytes(n, m);
+    *bytes = prec == SNG_FP32 ? plain_ws_bytes(n, m) : lowp_ws_bytes(n, m);
     return SNG_OK;
 }
 
@@ -292,11 +302,64 @@ int sng_dbscan(const float *X, int64_t n, int32_t d, int64_t ld, double s, doubl
     return run_plain(I, cfg, true, st);
 }
 
-int sng_dbscan_lowp(const float *, int64_t, int32_t, int64_t, const uint16_t *, int64_t, float,
-                    int32_t, double, double, int32_t, uint64_t, int32_t *, uint32_t *, void *,
-                    size_t, const sng_config *, void *)
+int sng_dbscan_lowp(const float *X, int64_t n, int32_t d, int64_t ld, const uint16_t *X_lp,
+                    int64_t ld_lp, float lp_scale, int32_t prec, double s, double eps,
+                    int32_t min_pts, uint64_t seed, int32_t *labels, uint32_t *degrees,
+                    void *workspace, size_t ws_bytes, const sng_config *cfg, void *stream)
 {
-    return SNG_ENOTIMPL;
+    (void)cfg;
+    int rc = check_points(X, n, d, ld);
+    if (rc) return rc;
+    if ((rc = check_eps(eps))) return rc;
+    if (prec != SNG_BF16 && prec != SNG_FP16) return SNG_EINVAL;
+    if (!(lp_scale == lp_scale) || __builtin_isinf(lp_scale) || lp_scale == 0.0f) return SNG_EINVAL;
+    if (n > 0 && (!X_lp || ((uintptr_t)X_lp & 15u) || ld_lp < d || (ld_lp & 7))) return SNG_EINVAL;
+    if (d > 16384) return SNG_ENOTIMPL;
+    int64_t m = 0;
+    if ((rc = m_from_s(s, n, &m))) return rc;
+    if (n > 0 && !labels) return SNG_EINVAL;
+    if (n > 0 && (((uintptr_t)labels & 3u) || ((uintptr_t)degrees & 3u))) return SNG_EINVAL;
+    const size_t need = lowp_ws_bytes(n, m);
+    if (!workspace || ws_bytes < need) return SNG_EWORKSPACE;
+    hipStream_t st = (hipStream_t)stream;
+    Carve cv(workspace);
+    Inst I = make_inst(X, n, d, ld, m, eps, seed, min_pts);
+    I.cnt = cv.take<unsigned long long>(kHeaderBytes / 8);
+    uint32_t *wdeg = cv.take<uint32_t>((size_t)n);
+    I.core = cv.take<uint8_t>((size_t)n);
+    const uint64_t words = sizes_for(n, m).chunks * 8;
+    I.mask = cv.take<uint32_t>(words);
+    I.deg = degrees ? degrees : wdeg;
+    I.labels = labels;
+    LowpArgs L;
+    memset(&L, 0, sizeof(L));
+    L.Xlp = X_lp;
+    L.ld_lp = ld_lp;
+    L.scale = lp_scale;
+    L.scale2 = (double)lp_scale * (double)lp_scale;
+    L.stats = cv.take<double>((size_t)n * 4);
+    L.queue = cv.take<uint64_t>((size_t)n * (size_t)m);
+    L.qcap = (uint64_t)n * (uint64_t)m;
+    // FP32 accumulation of d exact products in any order, each rounding
+    // allowed twice the round-to-nearest error (directed rounding included)
+    const double ua = 0x1p-22;
+    L.gamma_acc = d * ua < 0.5 ? d * ua / (1.0 - d * ua) : 1e300;
+    L.gamma_norm = (2.0 * d + 24.0) * 0x1p-52;
+    L.tiny = (2.0 * d + 2.0) * 0x1p-126;
+    // error of the binary64 definition: |D - S| <= c*S + beta64
+    const double c = (d + 3.0) * 0x1p-53 / (1.0 - (d + 3.0) * 0x1p-53);
+    const double beta64 = (2.0 * d + 2.0) * 0x1p-1074;
+    L.eps2_lo = (I.eps2 - beta64) / (1.0 + c) * (1.0 - 0x1p-50);
+    L.eps2_hi = (I.eps2 + beta64) / (1.0 - c) * (1.0 + 0x1p-50);
+    SNG_TRY(init_header(I.cnt, (uint64_t)n * (uint64_t)m, c, st));
+    SNG_TRY(launch_fill_u32(I.deg, I.n, 0u, st));
+    SNG_TRY(launch_fill_u32(I.mask, words, 0u, st));
+    SNG_TRY(launch_lowp(I, L, prec, st));
+    SNG_TRY(launch_core_init(I, st));
+    if (I.m > 0)
+        SNG_TRY(launch_hook_mask(I, st));
+    SNG_TRY(launch_finalize(I, st));
+    return SNG_OK;
 }
 
 int sng_graph_workspace_size(int64_t n, size_t *bytes)

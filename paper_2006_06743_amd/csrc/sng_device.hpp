@@ -139,7 +139,6 @@ __device__ __forceinline__ uint32_t group_bcast(uint32_t v, int o)
     }
 }
 
-__device__ __forceinline__ float f_dpp(float v, int ctrl_dummy);
 
 template <int CTRL>
 __device__ __forceinline__ float dpp_f(float v)
@@ -187,6 +186,34 @@ __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
     for (int off = 32; off > 0; off >>= 1)
         v += __shfl_xor(v, off);
     return v;
+}
+
+// Adds K per-thread tallies into cnt[slot[k]] with one atomic per block and
+// counter (every thread of the block must call it; blockDim <= 1024).
+template <int K>
+__device__ __forceinline__ void block_count_add(unsigned long long *cnt, const int (&slot)[K],
+                                                const uint32_t (&mine)[K])
+{
+    __shared__ unsigned long long part[K][16];
+    const int w = threadIdx.x / kWave;
+    unsigned long long s[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+        s[k] = wave_sum_u64(mine[k]);
+    if (lane_id() == 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+            part[k][w] = s[k];
+    }
+    __syncthreads();
+    if (threadIdx.x < K && cnt) {
+        const int nw = (blockDim.x + kWave - 1) / kWave;
+        unsigned long long tot = 0;
+        for (int i = 0; i < nw; ++i)
+            tot += part[threadIdx.x][i];
+        if (tot)
+            atomicAdd(cnt + slot[threadIdx.x], tot);
+    }
 }
 
 // ---------------------------------------------------------------------------

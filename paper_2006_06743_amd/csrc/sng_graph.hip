@@ -30,11 +30,13 @@ __global__ void k_fill_u64(unsigned long long *p, uint64_t count, unsigned long 
         p[i] = v;
 }
 
+// Grid-stride launches: enough blocks to fill the chip, few enough that the
+// per-block counter atomics stay cheap.
 static unsigned grid_for(uint64_t items, unsigned block)
 {
     uint64_t g = (items + block - 1) / block;
-    if (g > 65536ull * 8)
-        g = 65536ull * 8;
+    if (g > 4096)
+        g = 4096;
     return (unsigned)(g ? g : 1);
 }
 
@@ -57,11 +59,9 @@ hipError_t launch_fill_u64(unsigned long long *p, uint64_t count, unsigned long 
 
 __device__ __forceinline__ void count_add(unsigned long long *cnt, int slot, uint32_t mine)
 {
-    if (!cnt)
-        return;
-    const unsigned long long s = wave_sum_u64(mine);
-    if (lane_id() == 0 && s)
-        atomicAdd(cnt + slot, s);
+    const int slots[1] = {slot};
+    const uint32_t v[1] = {mine};
+    block_count_add<1>(cnt, slots, v);
 }
 
 __global__ __launch_bounds__(256) void k_core_init(Inst I)

@@ -21,6 +21,23 @@ struct PassAShape {
 // Fills the binary32 band [lo, hi] around eps2 for dimension d.
 void band_fp32(double eps2, int d, float *lo, float *hi, double *rel);
 
+// Extra inputs of the mixed-precision pass.
+struct LowpArgs {
+    const uint16_t *Xlp;   // 16-bit copy, row stride ld_lp (multiple of 8), 16-byte aligned
+    int64_t ld_lp;
+    float scale;           // X ~= scale * X_lp
+    double scale2;         // scale^2
+    double *stats;         // [n][4]: ||v||^2, ||v||, r, pad (rounded up)
+    uint64_t *queue;       // undecided slots i*m + t
+    uint64_t qcap;
+    double eps2_lo, eps2_hi;  // S <= eps2_lo forces acceptance, S > eps2_hi rejection
+    double gamma_acc;      // relative error of the FP32 MFMA accumulation
+    double gamma_norm;     // relative error of the binary64 norms and their combination
+    double tiny;           // absolute slack for flushed subnormals
+};
+
+hipError_t launch_lowp(const Inst &I, const LowpArgs &L, int prec, hipStream_t st);
+
 // Resolves the launch shape for an instance (d, row alignment, user config).
 PassAShape resolve_shape(int d, bool vec_ok, int lanes_req, int cpw_req, int lds_req,
                          int prefetch_req);

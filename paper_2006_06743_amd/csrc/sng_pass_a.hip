@@ -323,7 +323,9 @@ __device__ __forceinline__ void pass_a_range(const Inst &I, uint64_t ch_lo, uint
         flush_source(gs, I.deg, q);
 }
 
-__device__ __forceinline__ void commit_tally(const Tally &t, unsigned long long *cnt)
+// One atomic per wave and counter (used where waves of a block work for
+// different instances).
+__device__ __forceinline__ void commit_tally_wave(const Tally &t, unsigned long long *cnt)
 {
     if (!cnt)
         return;
@@ -337,18 +339,24 @@ __device__ __forceinline__ void commit_tally(const Tally &t, unsigned long long 
     }
 }
 
+// One atomic per block and counter (all threads of the block call this).
+__device__ __forceinline__ void commit_tally(const Tally &t, unsigned long long *cnt)
+{
+    const int slots[3] = {kCntSelf, kCntAccepted, kCntRechecked};
+    const uint32_t v[3] = {t.self, t.accepted, t.rechecked};
+    block_count_add<3>(cnt, slots, v);
+}
+
 template <class Row, int OB>
 __global__ __launch_bounds__(256) void k_pass_a(Inst I, uint32_t cpw, uint32_t slice_floats)
 {
     extern __shared__ float lds[];
-    const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
-    const uint64_t lo = (uint64_t)wave * cpw;
-    if (lo >= I.chunks)
-        return;
-    const uint64_t hi = min(lo + cpw, I.chunks);
+    const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const uint64_t lo = wave * cpw;
     float *slice = lds + (threadIdx.x / kWave) * slice_floats;
     Tally t;
-    pass_a_range<Row, OB>(I, lo, hi, slice, t);
+    if (lo < I.chunks)  // wave-uniform
+        pass_a_range<Row, OB>(I, lo, min(lo + cpw, I.chunks), slice, t);
     commit_tally(t, I.cnt);
 }
 
@@ -361,8 +369,8 @@ __global__ __launch_bounds__(256) void k_pass_a_batch(const Inst *__restrict__ t
                                                       uint32_t slice_floats)
 {
     extern __shared__ float lds[];
-    const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
-    uint64_t lo = (uint64_t)wave * cpw;
+    const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    uint64_t lo = wave * cpw;
     if (lo >= total)
         return;
     const uint64_t hi = min(lo + cpw, total);
@@ -381,7 +389,7 @@ __global__ __launch_bounds__(256) void k_pass_a_batch(const Inst *__restrict__ t
         const uint64_t end = min(hi, starts[a + 1]);
         Tally t;
         pass_a_range<Row, OB>(I, lo - starts[a], end - starts[a], slice, t);
-        commit_tally(t, I.cnt);
+        commit_tally_wave(t, I.cnt);
         lo = end;
     }
 }

@@ -1,0 +1,132 @@
+"""GPU parity of the mixed-precision form (sng_dbscan_lowp): the 16-bit copy
+only filters; every undecided pair is re-decided in binary64, so degrees and
+labels must equal the oracle's bit for bit."""
+import numpy as np
+import pytest
+
+from paper_2006_06743_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sng():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2006_06743_amd as s
+    s.load()
+    return s
+
+
+def lp_tensor(bits: np.ndarray, pad_to: int = 8):
+    """uint16 [n, d] -> cuda int16 view [n, d] with row stride a multiple of 8."""
+    import torch
+    n, d = bits.shape
+    ld = (d + pad_to - 1) // pad_to * pad_to
+    buf = np.zeros((max(n, 1), ld), np.uint16)
+    buf[:n, :d] = bits
+    t = torch.from_numpy(buf.view(np.int16)).cuda()
+    return t[:n, :d] if n > 0 else t[:0, :d]
+
+
+def run_lowp(sng, X, bits, s, eps, min_pts, seed, prec, scale=1.0):
+    import torch
+    Xg = torch.from_numpy(np.ascontiguousarray(X)).cuda()
+    lab, deg, ws = sng.dbscan_lowp(Xg, lp_tensor(bits), s, eps, min_pts, seed, prec=prec,
+                                   lp_scale=scale)
+    torch.cuda.synchronize()
+    st = sng.stats(ws)
+    assert st.overflow == 0
+    return lab.cpu().numpy(), deg.cpu().numpy().view(np.uint32), st
+
+
+def assert_same(gl, gd, ref, what):
+    bad = np.nonzero(gd != ref.deg)[0]
+    assert bad.size == 0, "%s: %d degrees differ (first %s)" % (what, bad.size, bad[:5])
+    bad = np.nonzero(gl != ref.labels)[0]
+    assert bad.size == 0, "%s: %d labels differ (first %s)" % (what, bad.size, bad[:5])
+
+
+def bits_for(X, prec, scale=1.0):
+    Y = (X / np.float32(scale)).astype(np.float32)
+    return wl.bf16_bits(Y) if prec == 1 else wl.fp16_bits(Y)
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("prec", [1, 2], ids=["bf16", "fp16"])
+def test_mnistlike_784d_full(sng, orc, prec):
+    W = wl.mnistlike_784d()
+    print("case", W.name, "prec", prec, flush=True)
+    ref = orc.dbscan(W.X, W.eps, W.min_pts, W.seed, s=W.s)
+    gl, gd, st = run_lowp(sng, W.X, bits_for(W.X, prec), W.s, W.eps, W.min_pts, W.seed, prec)
+    assert_same(gl, gd, ref, "%s prec=%d" % (W.name, prec))
+    assert st.accepted == ref.accepted and st.n_clusters == ref.n_clusters
+    print("rechecked fraction %.5f" % (st.rechecked / st.slots), flush=True)
+    assert 0 < st.rechecked < 0.05 * st.slots
+
+
+def test_mnistlike_integer_copy(sng, orc):
+    """8-bit images: the copy holds the integers 0..255 exactly (scale 1/255)."""
+    W = wl.mnistlike_784d(n_per=1500)
+    eps = 3.9
+    q = W.meta["q"].astype(np.float32)
+    bits = wl.bf16_bits(q)
+    ref = orc.dbscan(W.X, eps, W.min_pts, W.seed, s=W.s)
+    gl, gd, st = run_lowp(sng, W.X, bits, W.s, eps, W.min_pts, W.seed, 1, scale=1.0 / 255.0)
+    assert_same(gl, gd, ref, "integer copy")
+    assert st.rechecked < 0.002 * st.slots
+
+
+CASES = []
+_rng = np.random.default_rng(4242)
+for _k in range(24):
+    CASES.append((_k, int(_rng.choice([1, 2, 40, 200, 1500])),
+                  int(_rng.choice([1, 3, 5, 16, 31, 32, 33, 64, 100, 257, 784, 1000])),
+                  str(_rng.choice(["blobs", "grid", "uniform", "dupes"])),
+                  float(_rng.choice([0.0, 0.01, 0.1, 0.5])), int(_rng.choice([1, 2]))))
+
+
+@pytest.mark.parametrize("case", CASES, ids=["r%d_n%d_d%d_%s_s%g_p%d" % c for c in CASES])
+def test_random_instances(sng, orc, case):
+    k, n, d, kind, s, prec = case
+    rng = np.random.default_rng(700 + k)
+    X = wl.random_instance(rng, n, d, kind, spread=0.04)
+    seed = int(rng.integers(0, 2**63))
+    if n >= 2:
+        smp = X[rng.integers(0, n, 50)].astype(np.float64)
+        dd = np.sqrt(((smp[:, None] - smp[None]) ** 2).sum(-1))
+        eps = float(np.quantile(dd[dd > 0], 0.2)) if np.any(dd > 0) else 1.0
+    else:
+        eps = 1.0
+    print("case", case, "eps", eps, flush=True)
+    for min_pts in [0, 2, 4]:
+        ref = orc.dbscan(X, eps, min_pts, seed, s=s)
+        gl, gd, _ = run_lowp(sng, X, bits_for(X, prec), s, eps, min_pts, seed, prec)
+        assert_same(gl, gd, ref, "%s MinPts=%d" % (case, min_pts))
+
+
+@pytest.mark.parametrize("prec", [1, 2], ids=["bf16", "fp16"])
+def test_near_eps_adversarial(sng, orc, prec):
+    """Points on a sphere of radius eps: almost every pair with the centre is
+    undecided by the 16-bit filter and must come from the binary64 recheck."""
+    rng = np.random.default_rng(31)
+    for d in [3, 64, 300]:
+        u = rng.normal(size=(2000, d))
+        u /= np.linalg.norm(u, axis=1, keepdims=True)
+        eps = 0.8
+        X = np.vstack([np.zeros((300, d)), eps * u]).astype(np.float32)
+        ref = orc.dbscan(X, eps, 3, 8, s=0.3)
+        gl, gd, st = run_lowp(sng, X, bits_for(X, prec), 0.3, eps, 3, 8, prec)
+        assert_same(gl, gd, ref, "sphere d=%d prec=%d" % (d, prec))
+        assert st.rechecked > 0
+
+
+def test_bad_copy_still_exact(sng, orc):
+    """A copy that is far from X (wrong scale, NaNs) only costs rechecks."""
+    rng = np.random.default_rng(5)
+    X = wl.random_instance(rng, 800, 24, "blobs", spread=0.03)
+    bits = wl.bf16_bits(X * 1.7)
+    bits[::7, 3] = 0x7FC0  # NaN entries in the copy
+    ref = orc.dbscan(X, 0.06, 3, 2, s=0.2)
+    gl, gd, st = run_lowp(sng, X, bits, 0.2, 0.06, 3, 2, 1)
+    assert_same(gl, gd, ref, "bad copy")
