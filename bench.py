@@ -24,6 +24,7 @@ HBM_PEAK_GBS = 8000.0
 METRIC = "sampled pair-distance evals/sec + end-to-end cluster time (plain vs mixed/batched)"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pass_a_gmm16d_traffic.json")
 PASS_A_SOURCES = ["paper_2006_06743_amd/csrc/sng_pass_a.hip",
+                  "paper_2006_06743_amd/csrc/sng_pass_a.hpp",
                   "paper_2006_06743_amd/csrc/sng_device.hpp"]
 
 

@@ -57,9 +57,14 @@ def _stream(t: torch.Tensor) -> int:
 
 
 def _rows(X: torch.Tensor):
-    if not X.is_cuda or X.dtype != torch.float32 or X.dim() != 2 or X.stride(1) != 1:
-        raise ValueError("X must be a CUDA float32 tensor [n, d] with unit column stride")
-    return X.shape[0], X.shape[1], X.stride(0) if X.shape[0] > 0 else X.shape[1]
+    """(n, d, row stride) of a CUDA float32 matrix with unit column stride
+    (strides of empty or single-row matrices are irrelevant)."""
+    if not X.is_cuda or X.dtype != torch.float32 or X.dim() != 2:
+        raise ValueError("X must be a CUDA float32 tensor [n, d]")
+    n, d = X.shape
+    if n > 0 and d > 1 and X.stride(1) != 1:
+        raise ValueError("X must have unit column stride")
+    return n, d, X.stride(0) if n > 1 else d
 
 
 def _ws(nbytes: int, device) -> torch.Tensor:

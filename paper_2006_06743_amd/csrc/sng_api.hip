@@ -3,6 +3,8 @@
 #include <math.h>
 #include <string.h>
 
+#include <vector>
+
 #include "../../include/sng.h"
 #include "sng_internal.hpp"
 
@@ -11,6 +13,7 @@ using namespace sng;
 namespace {
 
 constexpr size_t kHeaderBytes = 4096;  // counters of one instance
+constexpr size_t kInstHeader = 256;    // counters of instance k sit at k*256 in a batch
 constexpr size_t kAlign = 256;
 constexpr int64_t kMaxN = 2147483647LL;
 constexpr int64_t kMaxM = 2147483648LL;  // t/4 and 4*C stay in 32 bits
@@ -119,7 +122,7 @@ Inst make_inst(const float *X, int64_t n, int32_t d, int64_t ld, int64_t m, doub
     I.inv_n = n > 0 ? 1.0 / (double)n : 0.0;
     I.inv_C = z.C > 0 ? 1.0 / (double)z.C : 0.0;
     I.eps2 = eps * eps;
-    band_fp32(I.eps2, d, &I.lo, &I.hi, nullptr);
+    band_fp32(I.eps2, d, &I.lo, &I.hi, &I.band);
     I.calls = z.calls;
     I.chunks = z.chunks;
     I.chunk0 = 0;
@@ -406,47 +409,303 @@ int sng_graph_labels(int64_t n, const int32_t *edges, int64_t n_edges, int32_t m
     return SNG_OK;
 }
 
-int sng_sweep_workspace_size(int64_t, int32_t, int64_t, int32_t, int32_t, size_t *bytes)
+static size_t sweep_ws_bytes(int64_t n, int64_t m, int32_t K, int32_t P)
 {
-    if (bytes)
-        *bytes = 0;
-    return SNG_ENOTIMPL;
+    const Sizes z = sizes_for(n, m);
+    size_t b = kHeaderBytes;
+    b = align_up(b + (size_t)n * (size_t)K * 4);  // level histograms
+    b = align_up(b + z.chunks * 64 * 4);          // level codes per call
+    b = align_up(b + (size_t)n * (size_t)P);      // core levels
+    return b;
 }
 
-int sng_dbscan_sweep(const float *, int64_t, int32_t, int64_t, double, const double *, int32_t,
-                     const int32_t *, int32_t, uint64_t, int32_t *, uint32_t *, void *, size_t,
-                     void *)
+int sng_sweep_workspace_size(int64_t n, int32_t d, int64_t m, int32_t n_eps, int32_t n_minpts,
+                             size_t *bytes)
 {
-    return SNG_ENOTIMPL;
+    if (!bytes || n < 0 || d < 1 || m < 0 || n_eps < 1 || n_minpts < 1)
+        return SNG_EINVAL;
+    if (n > kMaxN || m > kMaxM || n_eps > kSweepMaxK || n_minpts > kSweepMaxP)
+        return SNG_ERANGE;
+    *bytes = sweep_ws_bytes(n, m, n_eps, n_minpts);
+    return SNG_OK;
 }
 
-int sng_batch_workspace_size(int32_t, const int64_t *, int32_t, const double *, size_t *bytes)
+int sng_dbscan_sweep(const float *X, int64_t n, int32_t d, int64_t ld, double s,
+                     const double *eps, int32_t n_eps, const int32_t *min_pts, int32_t n_minpts,
+                     uint64_t seed, int32_t *labels, uint32_t *degrees, void *workspace,
+                     size_t ws_bytes, void *stream)
 {
-    if (bytes)
-        *bytes = 0;
-    return SNG_ENOTIMPL;
+    int rc = check_points(X, n, d, ld);
+    if (rc) return rc;
+    if (!eps || !min_pts || n_eps < 1 || n_minpts < 1) return SNG_EINVAL;
+    if (n_eps > kSweepMaxK || n_minpts > kSweepMaxP) return SNG_ERANGE;
+    for (int k = 0; k < n_eps; ++k) {
+        if ((rc = check_eps(eps[k]))) return rc;
+        if (k > 0 && !(eps[k] > eps[k - 1])) return SNG_EINVAL;  // strictly increasing
+    }
+    int64_t m = 0;
+    if ((rc = m_from_s(s, n, &m))) return rc;
+    if (n > 0 && !labels) return SNG_EINVAL;
+    if ((uint64_t)n * (uint64_t)n_eps * (uint64_t)n_minpts > ((uint64_t)1 << 40)) return SNG_ERANGE;
+    const size_t need = sweep_ws_bytes(n, m, n_eps, n_minpts);
+    if (!workspace || ws_bytes < need) return SNG_EWORKSPACE;
+    hipStream_t st = (hipStream_t)stream;
+    Carve cv(workspace);
+    Inst I = make_inst(X, n, d, ld, m, eps[n_eps - 1], seed, 0);
+    I.cnt = cv.take<unsigned long long>(kHeaderBytes / 8);
+    SweepArgs S;
+    memset(&S, 0, sizeof(S));
+    S.K = n_eps;
+    S.P = n_minpts;
+    for (int k = 0; k < n_eps; ++k) {
+        S.c.e2[k] = eps[k] * eps[k];
+        band_fp32(S.c.e2[k], d, &S.c.lo[k], &S.c.hi[k], nullptr);
+    }
+    for (int p = 0; p < n_minpts; ++p)
+        S.c.min_pts[p] = min_pts[p];
+    S.hist = cv.take<uint32_t>((size_t)n * n_eps);
+    S.codes = cv.take<uint32_t>(sizes_for(n, m).chunks * 64);
+    S.kc = cv.take<uint8_t>((size_t)n * n_minpts);
+    S.labels = labels;
+    S.degrees = degrees;
+    double band = 0.0;
+    {
+        float lo, hi;
+        band_fp32(S.c.e2[n_eps - 1], d, &lo, &hi, &band);
+    }
+    SNG_TRY(init_header(I.cnt, (uint64_t)n * (uint64_t)m, band, st));
+    SNG_TRY(launch_fill_u32(S.hist, (uint64_t)n * n_eps, 0u, st));
+    SNG_TRY(launch_sweep(I, S, shape_for(I, nullptr), st));
+    return SNG_OK;
 }
 
-int sng_dbscan_batch(int32_t, const float *const *, const int64_t *, int32_t, const int64_t *,
-                     const double *, const double *, const int32_t *, const uint64_t *,
-                     int32_t *const *, uint32_t *const *, void *, size_t, void *)
+}  // extern "C"
+
+namespace {
+
+// Host-side image of a batch: descriptors, prefix tables and where they go
+// in the workspace.
+struct BatchHost {
+    std::vector<Inst> insts;
+    std::vector<uint64_t> chunk_starts, pblk, wblk;
+    BatchGeom G;
+    Inst *dT = nullptr;
+    uint64_t *dChunk = nullptr, *dP = nullptr, *dW = nullptr;
+    bool vec_ok = true;
+    int d = 0;
+};
+
+size_t batch_layout(int32_t count, const int64_t *n, const int64_t *m, size_t *mask_words)
 {
-    return SNG_ENOTIMPL;
+    size_t b = align_up((size_t)count * kInstHeader);
+    b = align_up(b < kHeaderBytes ? kHeaderBytes : b);
+    b = align_up(b + (size_t)count * sizeof(Inst));
+    b = align_up(b + 3 * (size_t)(count + 1) * sizeof(uint64_t));
+    uint64_t chunks = 0;
+    for (int k = 0; k < count; ++k) {
+        b = align_up(b + (size_t)n[k] * 4);
+        b = align_up(b + (size_t)n[k]);
+        chunks += sizes_for(n[k], m[k]).chunks;
+    }
+    b = align_up(b + chunks * 8 * 4);
+    if (mask_words)
+        *mask_words = chunks * 8;
+    return b;
 }
 
-int sng_batch_plan_create(int32_t, const float *const *, const int64_t *, int32_t,
-                          const int64_t *, const double *, const double *, const int32_t *,
-                          const uint64_t *, int32_t *const *, uint32_t *const *, void *, size_t,
-                          void *, sng_batch_plan **plan)
+int batch_prepare(int32_t count, const float *const *X, const int64_t *n, int32_t d,
+                  const int64_t *ld, const double *s, const double *eps, const int32_t *min_pts,
+                  const uint64_t *seed, int32_t *const *labels, uint32_t *const *degrees,
+                  void *workspace, size_t ws_bytes, BatchHost &h)
 {
-    if (plan)
-        *plan = nullptr;
-    return SNG_ENOTIMPL;
+    if (count < 0 || (count > 0 && (!X || !n || !ld || !s || !eps || !min_pts || !seed || !labels)))
+        return SNG_EINVAL;
+    if (count > (1 << 20)) return SNG_ERANGE;
+    if (d < 1) return SNG_EINVAL;
+    std::vector<int64_t> ms(count);
+    for (int k = 0; k < count; ++k) {
+        int rc = check_points(X[k], n[k], d, ld[k]);
+        if (rc) return rc;
+        if ((rc = check_eps(eps[k]))) return rc;
+        if ((rc = m_from_s(s[k], n[k], &ms[k]))) return rc;
+        if (n[k] > 0 && (!labels[k] || ((uintptr_t)labels[k] & 3u))) return SNG_EINVAL;
+        if (degrees && ((uintptr_t)degrees[k] & 3u)) return SNG_EINVAL;
+    }
+    size_t words = 0;
+    const size_t need = batch_layout(count, n, ms.data(), &words);
+    if (!workspace || ws_bytes < need) return SNG_EWORKSPACE;
+    Carve cv(workspace);
+    char *headers = cv.take<char>((size_t)count * kInstHeader < kHeaderBytes
+                                      ? kHeaderBytes : (size_t)count * kInstHeader);
+    h.dT = cv.take<Inst>((size_t)count);
+    h.dChunk = cv.take<uint64_t>(3 * (size_t)(count + 1));
+    h.dP = h.dChunk + (count + 1);
+    h.dW = h.dP + (count + 1);
+    h.insts.resize(count);
+    h.chunk_starts.assign(count + 1, 0);
+    h.pblk.assign(count + 1, 0);
+    h.wblk.assign(count + 1, 0);
+    h.d = d;
+    uint64_t chunk = 0, pb = 0, wb = 0;
+    std::vector<uint32_t *> wdeg(count);
+    std::vector<uint8_t *> core(count);
+    for (int k = 0; k < count; ++k) {
+        wdeg[k] = cv.take<uint32_t>((size_t)n[k]);
+        core[k] = cv.take<uint8_t>((size_t)n[k]);
+    }
+    uint32_t *mask = cv.take<uint32_t>(words);
+    for (int k = 0; k < count; ++k) {
+        Inst I = make_inst(X[k], n[k], d, ld[k], ms[k], eps[k], seed[k], min_pts[k]);
+        I.cnt = reinterpret_cast<unsigned long long *>(headers + (size_t)k * kInstHeader);
+        I.deg = (degrees && degrees[k]) ? degrees[k] : wdeg[k];
+        I.core = core[k];
+        I.mask = mask;
+        I.labels = labels[k];
+        I.chunk0 = chunk;
+        h.chunk_starts[k] = chunk;
+        h.pblk[k] = pb;
+        h.wblk[k] = wb;
+        chunk += I.chunks;
+        const uint64_t nblk = ((uint64_t)n[k] + kPointsPerBlock - 1) / kPointsPerBlock;
+        pb += nblk ? nblk : 1;
+        wb += (I.chunks * 8 + kWordsPerBlock - 1) / kWordsPerBlock;
+        if (((uintptr_t)X[k] % 16) || (ld[k] % 4))
+            h.vec_ok = false;
+        h.insts[k] = I;
+    }
+    h.chunk_starts[count] = chunk;
+    h.pblk[count] = pb;
+    h.wblk[count] = wb;
+    h.G.count = count;
+    h.G.pblk = h.dP;
+    h.G.wblk = h.dW;
+    h.G.chunk_starts = h.dChunk;
+    h.G.total_pblocks = pb;
+    h.G.total_wblocks = wb;
+    h.G.total_chunks = chunk;
+    if (pb > 0x7FFFFFFFull || wb > 0x7FFFFFFFull) return SNG_ERANGE;
+    return SNG_OK;
 }
 
-int sng_batch_plan_launch(sng_batch_plan *, void *) { return SNG_ENOTIMPL; }
+// Host tables -> workspace. `sync` true: blocking copies (plan creation);
+// false: copies on `st`, then waits for them so the host tables may go.
+int batch_upload(const BatchHost &h, hipStream_t st)
+{
+    const int count = h.G.count;
+    if (count == 0)
+        return SNG_OK;
+    if (hipMemcpyAsync(h.dT, h.insts.data(), count * sizeof(Inst), hipMemcpyHostToDevice, st) !=
+            hipSuccess ||
+        hipMemcpyAsync(h.dChunk, h.chunk_starts.data(), (count + 1) * sizeof(uint64_t),
+                       hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(h.dP, h.pblk.data(), (count + 1) * sizeof(uint64_t),
+                       hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(h.dW, h.wblk.data(), (count + 1) * sizeof(uint64_t),
+                       hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return SNG_EHIP;
+    return SNG_OK;
+}
 
-int sng_batch_plan_destroy(sng_batch_plan *) { return SNG_OK; }
+}  // namespace
+
+struct sng_batch_plan {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipStream_t capture = nullptr;
+};
+
+extern "C" {
+
+int sng_batch_workspace_size(int32_t count, const int64_t *n, int32_t d, const double *s,
+                             size_t *bytes)
+{
+    if (!bytes || count < 0 || (count > 0 && (!n || !s)) || d < 1)
+        return SNG_EINVAL;
+    std::vector<int64_t> ms(count);
+    for (int k = 0; k < count; ++k) {
+        if (n[k] < 0) return SNG_EINVAL;
+        if (n[k] > kMaxN) return SNG_ERANGE;
+        const int rc = m_from_s(s[k], n[k], &ms[k]);
+        if (rc) return rc;
+    }
+    *bytes = batch_layout(count, n, ms.data(), nullptr);
+    return SNG_OK;
+}
+
+int sng_dbscan_batch(int32_t count, const float *const *X, const int64_t *n, int32_t d,
+                     const int64_t *ld, const double *s, const double *eps,
+                     const int32_t *min_pts, const uint64_t *seed, int32_t *const *labels,
+                     uint32_t *const *degrees, void *workspace, size_t ws_bytes, void *stream)
+{
+    BatchHost h;
+    int rc = batch_prepare(count, X, n, d, ld, s, eps, min_pts, seed, labels, degrees, workspace,
+                           ws_bytes, h);
+    if (rc) return rc;
+    if (count == 0) return SNG_OK;
+    hipStream_t st = (hipStream_t)stream;
+    if ((rc = batch_upload(h, st))) return rc;
+    const PassAShape sh = resolve_shape(d, h.vec_ok, 0, 0, 0, 0);
+    SNG_TRY(launch_batch(h.dT, h.G, d, h.vec_ok, sh, st));
+    return SNG_OK;
+}
+
+int sng_batch_plan_create(int32_t count, const float *const *X, const int64_t *n, int32_t d,
+                          const int64_t *ld, const double *s, const double *eps,
+                          const int32_t *min_pts, const uint64_t *seed, int32_t *const *labels,
+                          uint32_t *const *degrees, void *workspace, size_t ws_bytes,
+                          void *stream, sng_batch_plan **plan)
+{
+    if (!plan) return SNG_EINVAL;
+    *plan = nullptr;
+    BatchHost h;
+    int rc = batch_prepare(count, X, n, d, ld, s, eps, min_pts, seed, labels, degrees, workspace,
+                           ws_bytes, h);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    if ((rc = batch_upload(h, st))) return rc;
+    sng_batch_plan *p = new sng_batch_plan();
+    if (hipStreamCreateWithFlags(&p->capture, hipStreamNonBlocking) != hipSuccess) {
+        delete p;
+        return SNG_EHIP;
+    }
+    const PassAShape sh = resolve_shape(d, h.vec_ok, 0, 0, 0, 0);
+    bool ok = hipStreamBeginCapture(p->capture, hipStreamCaptureModeThreadLocal) == hipSuccess;
+    hipError_t le = hipSuccess;
+    if (ok)
+        le = launch_batch(h.dT, h.G, d, h.vec_ok, sh, p->capture);
+    if (ok)
+        ok = hipStreamEndCapture(p->capture, &p->graph) == hipSuccess && le == hipSuccess;
+    if (ok)
+        ok = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0) == hipSuccess;
+    if (!ok) {
+        sng_batch_plan_destroy(p);
+        return SNG_EHIP;
+    }
+    *plan = p;
+    return SNG_OK;
+}
+
+int sng_batch_plan_launch(sng_batch_plan *plan, void *stream)
+{
+    if (!plan || !plan->exec)
+        return SNG_EINVAL;
+    return hipGraphLaunch(plan->exec, (hipStream_t)stream) == hipSuccess ? SNG_OK : SNG_EHIP;
+}
+
+int sng_batch_plan_destroy(sng_batch_plan *plan)
+{
+    if (!plan)
+        return SNG_OK;
+    if (plan->exec)
+        hipGraphExecDestroy(plan->exec);
+    if (plan->graph)
+        hipGraphDestroy(plan->graph);
+    if (plan->capture)
+        hipStreamDestroy(plan->capture);
+    delete plan;
+    return SNG_OK;
+}
 
 int sng_stats_read(const void *workspace, int32_t index, sng_stats *out, void *stream)
 {
@@ -456,7 +715,7 @@ int sng_stats_read(const void *workspace, int32_t index, sng_stats *out, void *s
     if (hipStreamSynchronize(st) != hipSuccess)
         return SNG_EHIP;
     unsigned long long h[kCntNum + 1];
-    const char *src = (const char *)workspace + (size_t)index * 0;  // one header per workspace
+    const char *src = (const char *)workspace + (size_t)index * kInstHeader;
     if (hipMemcpy(h, src, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess)
         return SNG_EHIP;
     out->slots = h[kCntSlots];

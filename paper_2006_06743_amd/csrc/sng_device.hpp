@@ -49,6 +49,7 @@ struct Inst {
     unsigned long long *cnt;  // counters (kCntNum)
     int32_t min_pts;
     int32_t pad_;
+    double band;              // relative half-width of the binary32 band (reported)
 };
 
 // ---------------------------------------------------------------------------

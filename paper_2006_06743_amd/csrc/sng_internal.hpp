@@ -38,6 +38,42 @@ struct LowpArgs {
 
 hipError_t launch_lowp(const Inst &I, const LowpArgs &L, int prec, hipStream_t st);
 
+// Sweep over a grid of eps (ascending) and MinPts values. The per-level
+// thresholds travel by value in the kernel arguments.
+constexpr int kSweepMaxK = 64;
+constexpr int kSweepMaxP = 16;
+struct SweepConst {
+    float lo[kSweepMaxK];   // binary32 band of each eps_k^2
+    float hi[kSweepMaxK];
+    double e2[kSweepMaxK];  // fl64(eps_k^2)
+    int32_t min_pts[kSweepMaxP];
+};
+struct SweepArgs {
+    SweepConst c;
+    int K, P;
+    uint32_t *hist;      // [n][K] accepted slots per point and level
+    uint32_t *codes;     // per Philox call: four level codes (K = none)
+    uint8_t *kc;         // [P][n] first core level (K = never)
+    int32_t *labels;     // [P][K][n]
+    uint32_t *degrees;   // [K][n] or null
+};
+
+hipError_t launch_sweep(const Inst &I, const SweepArgs &S, const PassAShape &sh, hipStream_t st);
+
+// Geometry of a batch (device tables are exclusive prefixes, count+1 long).
+constexpr uint32_t kPointsPerBlock = 2048;  // points of one instance per block
+constexpr uint32_t kWordsPerBlock = 4096;   // accept words of one instance per block
+struct BatchGeom {
+    int count;
+    const uint64_t *pblk;          // point blocks per instance (at least one each)
+    const uint64_t *wblk;          // accept-word blocks per instance
+    const uint64_t *chunk_starts;  // 64-call chunks per instance
+    uint64_t total_pblocks, total_wblocks, total_chunks;
+};
+
+hipError_t launch_batch(const Inst *T, const BatchGeom &G, int d, bool vec_ok,
+                        const PassAShape &sh, hipStream_t st);
+
 // Resolves the launch shape for an instance (d, row alignment, user config).
 PassAShape resolve_shape(int d, bool vec_ok, int lanes_req, int cpw_req, int lds_req,
                          int prefetch_req);

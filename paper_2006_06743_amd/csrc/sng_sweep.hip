@@ -1,0 +1,268 @@
+// Hyperparameter sweep of SNG-DBSCAN: every (eps_k, MinPts_p) pair of a grid
+// from one sampled-distance pass. The graphs are nested in eps (a pair
+// accepted at eps_k is accepted at every larger eps) and the core sets are
+// nested in eps and in MinPts, which is what makes one pass enough:
+//   pass      level code of every slot: the smallest k with D <= eps_k^2
+//             (K if none), and per-point histograms of the codes, so that
+//             deg_k[i] = sum of the histogram of i up to k;
+//   levels    core level kc_p[i] = smallest k with deg_k[i] >= MinPts_p;
+//   hook      a slot with code b joins i and j in the union-find of level
+//             e = max(b, kc_p[i], kc_p[j]) (the first level at which it is a
+//             core-core edge), and offers a core endpoint to a non-core one
+//             at level max(b, kc_p[core]) while the other is still non-core;
+//   propagate for k = 0..K-2, every core point of level k is joined with its
+//             level-k root at level k+1, so level k+1 holds every edge of the
+//             levels below it;
+//   finalize  core labels are roots; a non-core point takes the prefix minimum
+//             of the offers up to k and the root of that core point.
+// labels[p][k] then equals the single run at (eps_k, MinPts_p).
+#include "sng_pass_a.hpp"
+
+namespace sng {
+
+// Level decision of one slot. Thresholds live in LDS.
+struct SweepPolicy {
+    uint32_t *hist;   // [n][K]
+    uint32_t *codes;  // one word of four level codes per Philox call
+    const float *lo;
+    const float *hi;
+    const double *e2;
+    int K;
+    float hi_max;
+    uint32_t own = 0;  // codes of this lane's own call
+
+    __device__ __forceinline__ void begin_chunk() { own = 0x01010101u * (uint32_t)K; }
+    __device__ __forceinline__ void flush_source(uint32_t, int) {}
+    __device__ __forceinline__ int decide(float F, const float *rowi, const float *rowj, int d,
+                                          Tally &t, int q)
+    {
+        if (!(F <= hi_max))
+            return K;  // beyond every band (or NaN): rejected at every level
+        int a = 0, b = K - 1;  // first k with F <= hi[k]
+        while (a < b) {
+            const int mid = (a + b) >> 1;
+            if (F <= hi[mid])
+                b = mid;
+            else
+                a = mid + 1;
+        }
+        if (F <= lo[a])
+            return a;  // surely accepted at a, surely rejected below a
+        t.rechecked += (q == 0);
+        const double D = sqdist_f64(rowi, rowj, d);
+        int k = a;
+        while (k < K && !(D <= e2[k]))
+            ++k;
+        return k;
+    }
+    __device__ __forceinline__ void record(int b, uint32_t i, uint32_t j, int q, int o, int w,
+                                           Tally &t)
+    {
+        if (b < K && q == 0) {
+            atomicAdd(hist + (uint64_t)i * K + b, 1u);
+            atomicAdd(hist + (uint64_t)j * K + b, 1u);
+            t.accepted += 1;
+        }
+        if (q == o)
+            own = (own & ~(0xFFu << (8 * w))) | ((uint32_t)b << (8 * w));
+    }
+    __device__ __forceinline__ void end_chunk(uint64_t gchunk, int lane)
+    {
+        codes[gchunk * 64ull + (uint64_t)lane] = own;
+    }
+};
+
+template <class Row, int OB>
+__global__ __launch_bounds__(256) void k_sweep_pass(Inst I, SweepArgs S, uint32_t cpw,
+                                                    uint32_t slice_floats)
+{
+    extern __shared__ float lds[];
+    __shared__ float s_lo[kSweepMaxK], s_hi[kSweepMaxK];
+    __shared__ double s_e2[kSweepMaxK];
+    for (int k = threadIdx.x; k < S.K; k += blockDim.x) {
+        s_lo[k] = S.c.lo[k];
+        s_hi[k] = S.c.hi[k];
+        s_e2[k] = S.c.e2[k];
+    }
+    __syncthreads();
+    SweepPolicy pol;
+    pol.hist = S.hist;
+    pol.codes = S.codes;
+    pol.lo = s_lo;
+    pol.hi = s_hi;
+    pol.e2 = s_e2;
+    pol.K = S.K;
+    pol.hi_max = S.c.hi[S.K - 1];
+    const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const uint64_t lo = wave * cpw;
+    float *slice = lds + (threadIdx.x / kWave) * slice_floats;
+    Tally t;
+    if (lo < I.chunks)  // wave-uniform
+        pass_a_range<Row, OB>(I, pol, lo, min(lo + cpw, I.chunks), slice, t);
+    commit_tally(t, I.cnt);
+}
+
+__device__ __forceinline__ int32_t *level_labels(const SweepArgs &S, uint32_t n, int p, int k)
+{
+    return S.labels + ((uint64_t)p * S.K + (uint64_t)k) * n;
+}
+
+// Degrees per level, core levels per MinPts, and the initial label arrays
+// (parent = self for points that are core at that level, "no offer" else).
+__global__ __launch_bounds__(256) void k_sweep_levels(Inst I, SweepArgs S)
+{
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < I.n;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        uint8_t kc[kSweepMaxP];
+        for (int p = 0; p < S.P; ++p)
+            kc[p] = (uint8_t)S.K;
+        uint64_t run = 0;
+        for (int k = 0; k < S.K; ++k) {
+            run += S.hist[i * S.K + k];
+            if (S.degrees)
+                S.degrees[(uint64_t)k * I.n + i] = (uint32_t)run;
+            for (int p = 0; p < S.P; ++p)
+                if (kc[p] == S.K && (int64_t)run >= (int64_t)S.c.min_pts[p])
+                    kc[p] = (uint8_t)k;
+        }
+        for (int p = 0; p < S.P; ++p) {
+            S.kc[(uint64_t)p * I.n + i] = kc[p];
+            for (int k = 0; k < S.K; ++k)
+                level_labels(S, I.n, p, k)[i] = (kc[p] <= k) ? (int32_t)i : kNoCore;
+        }
+    }
+}
+
+// One thread per Philox call: regenerate the partners of its accepted slots.
+__global__ __launch_bounds__(256) void k_sweep_hook(Inst I, SweepArgs S)
+{
+    for (uint64_t call = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; call < I.calls;
+         call += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t word = S.codes[call];
+        if (word == 0x01010101u * (uint32_t)S.K)
+            continue;
+        const uint32_t i = (uint32_t)(call / I.C);
+        const uint32_t c = (uint32_t)(call - (uint64_t)i * I.C);
+        const Words4 W = philox10(c, i, I.key0, I.key1);
+        for (int w = 0; w < 4; ++w) {
+            const int b = (word >> (8 * w)) & 0xFF;
+            if (b >= S.K)
+                continue;
+            const uint32_t j = mod_exact(W.w[w], I.n, I.inv_n);
+            for (int p = 0; p < S.P; ++p) {
+                const int ki = S.kc[(uint64_t)p * I.n + i];
+                const int kj = S.kc[(uint64_t)p * I.n + j];
+                const int e = max(b, max(ki, kj));
+                if (e < S.K)
+                    uf_unite(level_labels(S, I.n, p, e), (int32_t)i, (int32_t)j);
+                const int ei = max(b, ki);  // i is a core neighbour of j from ei on
+                if (ei < kj)
+                    atomicMin(level_labels(S, I.n, p, ei) + j, (int32_t)i);
+                const int ej = max(b, kj);
+                if (ej < ki)
+                    atomicMin(level_labels(S, I.n, p, ej) + i, (int32_t)j);
+            }
+        }
+    }
+}
+
+// Level k -> k+1: join every core point of level k with its level-k root.
+__global__ __launch_bounds__(256) void k_sweep_propagate(Inst I, SweepArgs S, int k)
+{
+    const uint64_t total = (uint64_t)S.P * I.n;
+    for (uint64_t u = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; u < total;
+         u += (uint64_t)gridDim.x * blockDim.x) {
+        const int p = (int)(u / I.n);
+        const uint32_t x = (uint32_t)(u - (uint64_t)p * I.n);
+        if (S.kc[u] > k)
+            continue;
+        const int32_t r = uf_find(level_labels(S, I.n, p, k), (int32_t)x);
+        if (r != (int32_t)x)
+            uf_unite(level_labels(S, I.n, p, k + 1), (int32_t)x, r);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_sweep_compress(Inst I, SweepArgs S)
+{
+    const uint64_t total = (uint64_t)S.P * S.K * I.n;
+    for (uint64_t u = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; u < total;
+         u += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t pk = u / I.n;
+        const uint32_t x = (uint32_t)(u - pk * I.n);
+        const int p = (int)(pk / S.K), k = (int)(pk - (uint64_t)p * S.K);
+        if (S.kc[(uint64_t)p * I.n + x] <= k) {
+            int32_t *L = level_labels(S, I.n, p, k);
+            st_relaxed(L + x, uf_find(L, (int32_t)x));
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_sweep_borders(Inst I, SweepArgs S)
+{
+    const uint64_t total = (uint64_t)S.P * I.n;
+    for (uint64_t u = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; u < total;
+         u += (uint64_t)gridDim.x * blockDim.x) {
+        const int p = (int)(u / I.n);
+        const uint32_t x = (uint32_t)(u - (uint64_t)p * I.n);
+        const int kc = S.kc[u];
+        int32_t best = kNoCore;
+        for (int k = 0; k < kc && k < S.K; ++k) {
+            int32_t *L = level_labels(S, I.n, p, k);
+            const int32_t offer = L[x];
+            best = min(best, offer);
+            L[x] = (best == kNoCore) ? -1 : L[best];
+        }
+    }
+}
+
+static unsigned sweep_grid(uint64_t items)
+{
+    const uint64_t g = (items + 255) / 256;
+    return (unsigned)(g == 0 ? 1 : (g > 8192 ? 8192 : g));
+}
+
+hipError_t launch_sweep(const Inst &I, const SweepArgs &S, const PassAShape &sh, hipStream_t st)
+{
+    hipError_t e;
+    if (I.n == 0)
+        return hipSuccess;
+    if (I.m > 0 && I.chunks > 0) {
+        const bool vec_ok = ((uintptr_t)I.X % 16 == 0) && (I.ld % 4 == 0);
+        e = dispatch(I.d, vec_ok, sh, [&]<class Row, int OB>(uint32_t slice) -> hipError_t {
+            const uint64_t waves = (I.chunks + sh.chunks_per_wave - 1) / sh.chunks_per_wave;
+            const uint64_t blocks = (waves + sh.waves_per_block - 1) / sh.waves_per_block;
+            if (blocks > 0x7FFFFFFFull)
+                return hipErrorInvalidValue;
+            const size_t lds = (size_t)slice * sizeof(float) * sh.waves_per_block;
+            hipLaunchKernelGGL((k_sweep_pass<Row, OB>), dim3((unsigned)blocks),
+                               dim3(64 * sh.waves_per_block), lds, st, I, S,
+                               (uint32_t)sh.chunks_per_wave, slice);
+            return hipGetLastError();
+        });
+        if (e != hipSuccess)
+            return e;
+    }
+    hipLaunchKernelGGL(k_sweep_levels, dim3(sweep_grid(I.n)), dim3(256), 0, st, I, S);
+    if ((e = hipGetLastError()) != hipSuccess)
+        return e;
+    if (I.m > 0) {
+        hipLaunchKernelGGL(k_sweep_hook, dim3(sweep_grid(I.calls)), dim3(256), 0, st, I, S);
+        if ((e = hipGetLastError()) != hipSuccess)
+            return e;
+    }
+    for (int k = 0; k + 1 < S.K; ++k) {
+        hipLaunchKernelGGL(k_sweep_propagate, dim3(sweep_grid((uint64_t)S.P * I.n)), dim3(256), 0,
+                           st, I, S, k);
+        if ((e = hipGetLastError()) != hipSuccess)
+            return e;
+    }
+    hipLaunchKernelGGL(k_sweep_compress, dim3(sweep_grid((uint64_t)S.P * S.K * I.n)), dim3(256),
+                       0, st, I, S);
+    if ((e = hipGetLastError()) != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(k_sweep_borders, dim3(sweep_grid((uint64_t)S.P * I.n)), dim3(256), 0, st,
+                       I, S);
+    return hipGetLastError();
+}
+
+}  // namespace sng
