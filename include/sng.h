@@ -80,7 +80,19 @@ typedef struct {
     int32_t chunks_per_wave; /* 64-call chunks processed by one wavefront */
     int32_t stage_lds;       /* 1: keep the source row in LDS instead of VGPRs */
     int32_t prefetch;        /* partner rows a group gathers ahead: 4, 8 or 16 */
+    int32_t schedule;        /* 0 auto, 1 direct gathers, 2 partner-block (L2 reuse) */
 } sng_config;
+/* schedule: the partner-block form sorts the sample slots by partner block
+ * before gathering, so rows narrower than a 128-byte line are reused from
+ * L2. It covers d <= 32 and at most 1024 partner blocks, a block being the
+ * largest power of two of rows, at most 2^16, whose d*4-byte rows fit in
+ * 512 KB (so n <= 2^25 at d = 3, n <= 2^23 at d = 16); auto picks
+ * it for d < 32 when X (n*d*4 bytes) exceeds 8 MB and the workspace holds
+ * its records, direct gathers otherwise. stage_lds implies direct gathers. */
+
+/* Flag for sng_workspace_size: size for the direct schedule only (smaller;
+ * a workspace of that size makes the automatic schedule choose it). */
+#define SNG_WS_DIRECT 0x100
 
 /* Device-side counters, copied out by sng_stats_read. */
 typedef struct {
@@ -102,8 +114,10 @@ const char *sng_status_string(int status);
  * >= 0, n >= 0. Host call, no device work. */
 int sng_samples_per_point(double s, int64_t n, int64_t *m);
 
-/* Bytes of workspace for sng_dbscan / sng_degrees with n points of
- * dimension d and m samples per point, at precision `prec`. Host call. */
+/* Bytes of workspace for sng_dbscan / sng_degrees / sng_cluster with n points
+ * of dimension d and m samples per point, at precision `prec` (optionally
+ * or-ed with SNG_WS_DIRECT). The partner-block schedule keeps 4 bytes per
+ * sample slot of records in the workspace. Host call. */
 int sng_workspace_size(int64_t n, int32_t d, int64_t m, int32_t prec, size_t *bytes);
 
 /* Sampling step only (Algorithm 1, graph construction; edges are not stored):
@@ -158,7 +172,7 @@ int sng_sweep_workspace_size(int64_t n, int32_t d, int64_t m, int32_t n_eps, int
 int sng_dbscan_sweep(const float *X, int64_t n, int32_t d, int64_t ld, double s,
                      const double *eps, int32_t n_eps, const int32_t *min_pts, int32_t n_minpts,
                      uint64_t seed, int32_t *labels, uint32_t *degrees, void *workspace,
-                     size_t ws_bytes, void *stream);
+                     size_t ws_bytes, const sng_config *cfg, void *stream);
 
 /* Batch of independent instances solved together (each equal to its own
  * sng_dbscan call). Arrays of length `count` are host arrays; X[k],

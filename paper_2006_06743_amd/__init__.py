@@ -33,10 +33,11 @@ class Config:
     chunks_per_wave: int = 0
     stage_lds: int = 0
     prefetch: int = 0
+    schedule: int = 0  # 0 auto, 1 direct gathers, 2 partner-block (L2 reuse)
 
     def c(self):
         return ctypes.byref(sng_config(self.lanes_per_pair, self.chunks_per_wave,
-                                       self.stage_lds, self.prefetch))
+                                       self.stage_lds, self.prefetch, self.schedule))
 
 
 @dataclass
@@ -185,7 +186,8 @@ def graph_labels(n: int, edges: torch.Tensor, min_pts: int, device=None):
 
 
 def sweep(X: torch.Tensor, s: float, eps_grid: Sequence[float], min_pts_grid: Sequence[int],
-          seed: int, want_degrees: bool = True, ws: Optional[torch.Tensor] = None):
+          seed: int, want_degrees: bool = True, ws: Optional[torch.Tensor] = None,
+          cfg: Optional[Config] = None):
     """All (eps, MinPts) pairs of a grid from one sampled-distance pass:
     labels [P][K][n] int32, degrees [K][n] (u32 bits) or None."""
     import numpy as np
@@ -204,7 +206,7 @@ def sweep(X: torch.Tensor, s: float, eps_grid: Sequence[float], min_pts_grid: Se
     check(_lib.load().sng_dbscan_sweep(X.data_ptr(), n, d, ld, float(s), eps.ctypes.data, K,
                                        mp.ctypes.data, P, int(seed), labels.data_ptr(),
                                        deg.data_ptr() if deg is not None else None,
-                                       ws.data_ptr(), ws.numel(), _stream(X)),
+                                       ws.data_ptr(), ws.numel(), _cfg(cfg), _stream(X)),
           "sng_dbscan_sweep")
     return labels, deg, ws
 

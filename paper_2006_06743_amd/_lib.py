@@ -27,7 +27,8 @@ EXPORTS = [
 
 class sng_config(ctypes.Structure):
     _fields_ = [("lanes_per_pair", ctypes.c_int32), ("chunks_per_wave", ctypes.c_int32),
-                ("stage_lds", ctypes.c_int32), ("prefetch", ctypes.c_int32)]
+                ("stage_lds", ctypes.c_int32), ("prefetch", ctypes.c_int32),
+                ("schedule", ctypes.c_int32)]
 
 
 class sng_stats(ctypes.Structure):
@@ -73,7 +74,7 @@ def load() -> ctypes.CDLL:
         "sng_graph_labels": ([i64, P, i64, i32, P, P, P, sz, P], ctypes.c_int),
         "sng_sweep_workspace_size": ([i64, i32, i64, i32, i32, ctypes.POINTER(sz)],
                                      ctypes.c_int),
-        "sng_dbscan_sweep": ([P, i64, i32, i64, dbl, P, i32, P, i32, u64, P, P, P, sz, P],
+        "sng_dbscan_sweep": ([P, i64, i32, i64, dbl, P, i32, P, i32, u64, P, P, P, sz, cfgp, P],
                              ctypes.c_int),
         "sng_batch_workspace_size": ([i32, P, i32, P, ctypes.POINTER(sz)], ctypes.c_int),
         "sng_dbscan_batch": ([i32, P, P, i32, P, P, P, P, P, P, P, P, sz, P], ctypes.c_int),

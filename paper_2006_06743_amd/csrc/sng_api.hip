@@ -149,6 +149,8 @@ int check_cfg(const sng_config *cfg)
         return SNG_EINVAL;
     if (cfg->prefetch != 0 && cfg->prefetch != 4 && cfg->prefetch != 8 && cfg->prefetch != 16)
         return SNG_EINVAL;
+    if (cfg->schedule < 0 || cfg->schedule > 2)
+        return SNG_EINVAL;
     return SNG_OK;
 }
 
@@ -167,8 +169,34 @@ hipError_t init_header(unsigned long long *cnt, uint64_t slots, double band, hip
     return hipGetLastError();
 }
 
+// Chooses the schedule of the sampled-distance pass: the partner-block
+// schedule when it applies, the caller allows it and the workspace holds its
+// records (carved after `used` bytes); otherwise direct gathers.
+int pick_bucket(const Inst &I, const sng_config *cfg, void *workspace, size_t ws_bytes,
+                size_t used, BucketGeom *B, bool *use)
+{
+    *use = false;
+    if (I.m == 0 || I.n == 0)
+        return SNG_OK;  // no sampled-distance pass to schedule
+    const int sched = cfg ? cfg->schedule : 0;
+    if (sched == 1 || (cfg && cfg->stage_lds))
+        return sched == 2 ? SNG_EINVAL : SNG_OK;
+    if (!bucket_geometry(I.n, I.d, I.m, sched == 2, B))
+        return sched == 2 ? SNG_ENOTIMPL : SNG_OK;
+    if (align_up(used + bucket_bytes(*B)) > ws_bytes)
+        return sched == 2 ? SNG_EWORKSPACE : SNG_OK;
+    Carve cv((char *)workspace + used);
+    B->rec = cv.take<uint32_t>(B->gen_waves * B->region);
+    B->seg = cv.take<uint32_t>(B->gen_waves * B->NJ * 2);
+    B->start = cv.take<uint32_t>(B->gen_waves * 2);
+    B->queue = cv.take<unsigned long long>(kXcds);
+    *use = true;
+    return SNG_OK;
+}
+
 // Pass (a) plus post-processing for one carved instance.
-int run_plain(Inst &I, const sng_config *cfg, bool labels_wanted, hipStream_t st)
+int run_plain(Inst &I, const sng_config *cfg, bool labels_wanted, const BucketGeom *B,
+              hipStream_t st)
 {
     double band = 0.0;
     {
@@ -177,8 +205,12 @@ int run_plain(Inst &I, const sng_config *cfg, bool labels_wanted, hipStream_t st
     }
     SNG_TRY(init_header(I.cnt, (uint64_t)I.n * I.m, band, st));
     SNG_TRY(launch_fill_u32(I.deg, I.n, 0u, st));
-    if (I.m > 0)
+    if (I.m > 0 && B) {
+        SNG_TRY(launch_fill_u32(I.mask, I.chunks * 8, 0u, st));
+        SNG_TRY(launch_bucket_plain(I, *B, shape_for(I, cfg), st));
+    } else if (I.m > 0) {
         SNG_TRY(launch_pass_a(I, shape_for(I, cfg), st));
+    }
     if (!labels_wanted)
         return SNG_OK;
     SNG_TRY(launch_core_init(I, st));
@@ -219,9 +251,19 @@ int sng_workspace_size(int64_t n, int32_t d, int64_t m, int32_t prec, size_t *by
         return SNG_EINVAL;
     if (n > kMaxN || m > kMaxM)
         return SNG_ERANGE;
+    const bool direct_only = (prec & SNG_WS_DIRECT) != 0;
+    prec &= ~SNG_WS_DIRECT;
     if (prec != SNG_FP32 && prec != SNG_BF16 && prec != SNG_FP16)
         return SNG_EINVAL;
-    *bytes = prec == SNG_FP32 ? plain_ws_bytes(n, m) : lowp_ws_bytes(n, m);
+    if (prec != SNG_FP32) {
+        *bytes = lowp_ws_bytes(n, m);
+        return SNG_OK;
+    }
+    size_t b = plain_ws_bytes(n, m);
+    BucketGeom g;
+    if (!direct_only && bucket_geometry(n, d, m, true, &g))
+        b = align_up(b + bucket_bytes(g));
+    *bytes = b;
     return SNG_OK;
 }
 
@@ -247,7 +289,10 @@ int sng_degrees(const float *X, int64_t n, int32_t d, int64_t ld, int64_t m, dou
     I.mask = cv.take<uint32_t>(sizes_for(n, m).chunks * 8);
     I.deg = degrees;
     I.labels = nullptr;
-    return run_plain(I, cfg, false, st);
+    BucketGeom B;
+    bool use = false;
+    if ((rc = pick_bucket(I, cfg, workspace, ws_bytes, cv.off, &B, &use))) return rc;
+    return run_plain(I, cfg, false, use ? &B : nullptr, st);
 }
 
 int sng_cluster(const float *X, int64_t n, int32_t d, int64_t ld, int64_t m, double eps,
@@ -302,7 +347,10 @@ int sng_dbscan(const float *X, int64_t n, int32_t d, int64_t ld, double s, doubl
     I.mask = cv.take<uint32_t>(sizes_for(n, m).chunks * 8);
     I.deg = degrees ? degrees : wdeg;
     I.labels = labels;
-    return run_plain(I, cfg, true, st);
+    BucketGeom B;
+    bool use = false;
+    if ((rc = pick_bucket(I, cfg, workspace, ws_bytes, cv.off, &B, &use))) return rc;
+    return run_plain(I, cfg, true, use ? &B : nullptr, st);
 }
 
 int sng_dbscan_lowp(const float *X, int64_t n, int32_t d, int64_t ld, const uint16_t *X_lp,
@@ -419,6 +467,15 @@ static size_t sweep_ws_bytes(int64_t n, int64_t m, int32_t K, int32_t P)
     return b;
 }
 
+static size_t sweep_ws_bytes_full(int64_t n, int32_t d, int64_t m, int32_t K, int32_t P)
+{
+    size_t b = sweep_ws_bytes(n, m, K, P);
+    BucketGeom g;
+    if (bucket_geometry(n, d, m, true, &g))
+        b = align_up(b + bucket_bytes(g));
+    return b;
+}
+
 int sng_sweep_workspace_size(int64_t n, int32_t d, int64_t m, int32_t n_eps, int32_t n_minpts,
                              size_t *bytes)
 {
@@ -426,17 +483,18 @@ int sng_sweep_workspace_size(int64_t n, int32_t d, int64_t m, int32_t n_eps, int
         return SNG_EINVAL;
     if (n > kMaxN || m > kMaxM || n_eps > kSweepMaxK || n_minpts > kSweepMaxP)
         return SNG_ERANGE;
-    *bytes = sweep_ws_bytes(n, m, n_eps, n_minpts);
+    *bytes = sweep_ws_bytes_full(n, d, m, n_eps, n_minpts);
     return SNG_OK;
 }
 
 int sng_dbscan_sweep(const float *X, int64_t n, int32_t d, int64_t ld, double s,
                      const double *eps, int32_t n_eps, const int32_t *min_pts, int32_t n_minpts,
                      uint64_t seed, int32_t *labels, uint32_t *degrees, void *workspace,
-                     size_t ws_bytes, void *stream)
+                     size_t ws_bytes, const sng_config *cfg, void *stream)
 {
     int rc = check_points(X, n, d, ld);
     if (rc) return rc;
+    if ((rc = check_cfg(cfg))) return rc;
     if (!eps || !min_pts || n_eps < 1 || n_minpts < 1) return SNG_EINVAL;
     if (n_eps > kSweepMaxK || n_minpts > kSweepMaxP) return SNG_ERANGE;
     for (int k = 0; k < n_eps; ++k) {
@@ -473,9 +531,12 @@ int sng_dbscan_sweep(const float *X, int64_t n, int32_t d, int64_t ld, double s,
         float lo, hi;
         band_fp32(S.c.e2[n_eps - 1], d, &lo, &hi, &band);
     }
+    BucketGeom B;
+    bool use = false;
+    if ((rc = pick_bucket(I, cfg, workspace, ws_bytes, cv.off, &B, &use))) return rc;
     SNG_TRY(init_header(I.cnt, (uint64_t)n * (uint64_t)m, band, st));
     SNG_TRY(launch_fill_u32(S.hist, (uint64_t)n * n_eps, 0u, st));
-    SNG_TRY(launch_sweep(I, S, shape_for(I, nullptr), st));
+    SNG_TRY(launch_sweep(I, S, shape_for(I, cfg), use ? &B : nullptr, st));
     return SNG_OK;
 }
 

@@ -58,7 +58,8 @@ struct SweepArgs {
     uint32_t *degrees;   // [K][n] or null
 };
 
-hipError_t launch_sweep(const Inst &I, const SweepArgs &S, const PassAShape &sh, hipStream_t st);
+hipError_t launch_sweep(const Inst &I, const SweepArgs &S, const PassAShape &sh,
+                        const struct BucketGeom *B, hipStream_t st);
 
 // Geometry of a batch (device tables are exclusive prefixes, count+1 long).
 constexpr uint32_t kPointsPerBlock = 2048;  // points of one instance per block
@@ -73,6 +74,27 @@ struct BatchGeom {
 
 hipError_t launch_batch(const Inst *T, const BatchGeom &G, int d, bool vec_ok,
                         const PassAShape &sh, hipStream_t st);
+
+// L2-reuse schedule of the sampled-distance pass (sng_bucket.hip).
+constexpr int kXcds = 8;                    // workgroup b runs on XCD b mod 8
+constexpr uint64_t kGenCalls = 16384;       // Philox calls per generator wavefront
+constexpr uint32_t kMaxPartnerBlocks = 1024;
+struct BucketGeom {
+    uint32_t bshift;     // partner block = 2^bshift rows
+    uint32_t NJ;         // partner blocks
+    uint64_t gen_waves;  // generator ranges
+    uint64_t region;     // records per generator range (capacity)
+    uint32_t *rec;       // [gen_waves][region] 4-byte slot records
+    uint32_t *seg;       // [gen_waves][NJ][2] segment offset and count
+    uint32_t *start;     // [gen_waves][2] source and call of each range's first call
+    unsigned long long *queue;  // [kXcds] next segment of each XCD's queue
+};
+bool bucket_geometry(int64_t n, int d, int64_t m, bool force, BucketGeom *g);
+size_t bucket_bytes(const BucketGeom &g);
+hipError_t launch_bucket_plain(const Inst &I, const BucketGeom &B, const PassAShape &sh,
+                               hipStream_t st);
+hipError_t launch_bucket_sweep(const Inst &I, const SweepArgs &S, const BucketGeom &B,
+                               const PassAShape &sh, hipStream_t st);
 
 // Resolves the launch shape for an instance (d, row alignment, user config).
 PassAShape resolve_shape(int d, bool vec_ok, int lanes_req, int cpw_req, int lds_req,

@@ -195,6 +195,10 @@ PassAShape resolve_shape(int d, bool vec_ok, int lanes_req, int cpw_req, int lds
                 g <<= 1;
         }
     }
+    if (!s.stage_lds && !vec_ok && !(g == 1 && d <= 8)) {
+        // scalar row policies exist for 4, 16 and 64 lanes
+        g = g <= 4 ? 4 : (g <= 16 ? 16 : 64);
+    }
     s.lanes = g;
     s.chunks_per_wave = cpw_req > 0 ? cpw_req : 8;
     int ob = prefetch_req > 0 ? prefetch_req / 4 : (g >= 2 ? 2 : 1);

@@ -35,10 +35,14 @@ struct SmallRow {
     }
     __device__ __forceinline__ float partial(const Buf &b, int, int) const
     {
+        return partial2(r, b, 0, D);
+    }
+    __device__ __forceinline__ static float partial2(const Buf &a, const Buf &b, int, int)
+    {
         float acc = 0.0f;
 #pragma unroll
         for (int k = 0; k < D; ++k) {
-            const float e = r.v[k] - b.v[k];
+            const float e = a.v[k] - b.v[k];
             acc = __builtin_fmaf(e, e, acc);
         }
         return acc;
@@ -74,14 +78,18 @@ struct VecRow {
     }
     __device__ __forceinline__ float partial(const Buf &b, int q, int d) const
     {
+        return partial2(r, b, q, d);
+    }
+    __device__ __forceinline__ static float partial2(const Buf &a, const Buf &b, int q, int d)
+    {
         float acc = 0.0f;
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
             const int k = 4 * (v * G + q);
-            const float e0 = r.v[v].x - b.v[v].x;
-            const float e1 = (FULL || k + 1 < d) ? r.v[v].y - b.v[v].y : 0.0f;
-            const float e2 = (FULL || k + 2 < d) ? r.v[v].z - b.v[v].z : 0.0f;
-            const float e3 = (FULL || k + 3 < d) ? r.v[v].w - b.v[v].w : 0.0f;
+            const float e0 = a.v[v].x - b.v[v].x;
+            const float e1 = (FULL || k + 1 < d) ? a.v[v].y - b.v[v].y : 0.0f;
+            const float e2 = (FULL || k + 2 < d) ? a.v[v].z - b.v[v].z : 0.0f;
+            const float e3 = (FULL || k + 3 < d) ? a.v[v].w - b.v[v].w : 0.0f;
             acc = __builtin_fmaf(e0, e0, acc);
             acc = __builtin_fmaf(e1, e1, acc);
             acc = __builtin_fmaf(e2, e2, acc);
@@ -115,12 +123,16 @@ struct ScalarRow {
     {
         r = fetch(row, q, d);
     }
-    __device__ __forceinline__ float partial(const Buf &b, int, int) const
+    __device__ __forceinline__ float partial(const Buf &b, int q, int d) const
+    {
+        return partial2(r, b, q, d);
+    }
+    __device__ __forceinline__ static float partial2(const Buf &a, const Buf &b, int, int)
     {
         float acc = 0.0f;
 #pragma unroll
         for (int v = 0; v < NS; ++v) {
-            const float e = r.v[v] - b.v[v];
+            const float e = a.v[v] - b.v[v];
             acc = __builtin_fmaf(e, e, acc);
         }
         return acc;

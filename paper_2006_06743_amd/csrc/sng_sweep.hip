@@ -221,12 +221,20 @@ static unsigned sweep_grid(uint64_t items)
     return (unsigned)(g == 0 ? 1 : (g > 8192 ? 8192 : g));
 }
 
-hipError_t launch_sweep(const Inst &I, const SweepArgs &S, const PassAShape &sh, hipStream_t st)
+hipError_t launch_sweep(const Inst &I, const SweepArgs &S, const PassAShape &sh,
+                        const BucketGeom *B, hipStream_t st)
 {
     hipError_t e;
     if (I.n == 0)
         return hipSuccess;
-    if (I.m > 0 && I.chunks > 0) {
+    if (I.m > 0 && I.chunks > 0 && B) {
+        e = launch_fill_u32(S.codes, I.chunks * 64, 0x01010101u * (uint32_t)S.K, st);
+        if (e != hipSuccess)
+            return e;
+        e = launch_bucket_sweep(I, S, *B, sh, st);
+        if (e != hipSuccess)
+            return e;
+    } else if (I.m > 0 && I.chunks > 0) {
         const bool vec_ok = ((uintptr_t)I.X % 16 == 0) && (I.ld % 4 == 0);
         e = dispatch(I.d, vec_ok, sh, [&]<class Row, int OB>(uint32_t slice) -> hipError_t {
             const uint64_t waves = (I.chunks + sh.chunks_per_wave - 1) / sh.chunks_per_wave;

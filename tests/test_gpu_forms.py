@@ -41,15 +41,18 @@ SWEEP_CASES = [
 ]
 
 
+@pytest.mark.parametrize("schedule", [1, 2], ids=["direct", "partner_blocks"])
 @pytest.mark.parametrize("case", SWEEP_CASES, ids=["s%d_n%d_d%d" % c[:3] for c in SWEEP_CASES])
-def test_sweep_equals_single_runs(sng, orc, case):
+def test_sweep_equals_single_runs(sng, orc, case, schedule):
     import torch
     k, n, d, eps, mps, s = case
+    if schedule == 2 and d > 32:
+        pytest.skip("partner-block schedule covers d <= 32")
     rng = np.random.default_rng(900 + k)
     X = wl.random_instance(rng, n, d, "blobs", spread=0.03)
     seed = int(rng.integers(0, 2**63))
-    print("case", case[:3], flush=True)
-    labels, degs, ws = sng.sweep(gpu(X), s, eps, mps, seed)
+    print("case", case[:3], "schedule", schedule, flush=True)
+    labels, degs, ws = sng.sweep(gpu(X), s, eps, mps, seed, cfg=sng.Config(schedule=schedule))
     torch.cuda.synchronize()
     L = labels.cpu().numpy()
     D = degs.cpu().numpy().view(np.uint32)

@@ -101,12 +101,13 @@ def test_every_launch_shape_is_identical(sng, orc, d):
     eps = 0.05 * np.sqrt(d)
     ref = orc.dbscan(X, eps, 3, 123, s=0.02)
     vec_pads = [0] if d % 4 == 0 else [0, 4 - d % 4]
-    shapes = [(lanes, cpw, lds, pf) for lanes in [0, 1, 2, 4, 8, 16, 32, 64]
+    shapes = [(lanes, cpw, lds, pf, sc) for lanes in [0, 1, 2, 4, 8, 16, 32, 64]
               for cpw in [1, 3, 64] for lds in [0, 1] for pf in [0, 4, 8, 16]
-              if not (lds and pf)]
-    for lanes, cpw, lds, pf in shapes:
+              for sc in ([0, 1, 2] if d <= 32 else [0, 1])
+              if not (lds and (pf or sc == 2))]
+    for lanes, cpw, lds, pf, sc in shapes:
         for pad in vec_pads:
-            cfg = sng.Config(lanes, cpw, lds, pf)
+            cfg = sng.Config(lanes, cpw, lds, pf, sc)
             print("shape d=%d cfg=%s pad=%d" % (d, cfg, pad), flush=True)
             gl, gd, _ = run(sng, X, 0.02, eps, 3, 123, cfg=cfg, pad=pad)
             assert_same(gl, gd, ref, "d=%d cfg=%s pad=%d" % (d, cfg, pad))
@@ -177,6 +178,21 @@ def test_recheck_band_adversarial(sng, orc):
         gl, gd, st = run(sng, G, 0.05, 2.0, 4, 5)
         ref = orc.dbscan(G, 2.0, 4, 5, s=0.05)
         assert_same(gl, gd, ref, "grid d=%d" % d)
+
+
+@pytest.mark.parametrize("schedule", [1, 2], ids=["direct", "partner_blocks"])
+def test_schedules_on_many_partner_blocks(sng, orc, schedule):
+    """Both schedules on an instance spanning many partner blocks (d=3, so
+    blocks of 2^16 rows; n=300k gives five blocks) and on ragged sizes."""
+    rng = np.random.default_rng(61)
+    for n, d, s in [(300_001, 3, 0.0004), (70_000, 16, 0.003), (40_000, 32, 0.004),
+                    (5, 2, 1.0), (1, 3, 2.0)]:
+        X = wl.random_instance(rng, n, d, "blobs", spread=0.002)
+        eps = 0.004 * np.sqrt(d)
+        ref = orc.dbscan(X, eps, 2, 77, s=s)
+        gl, gd, st = run(sng, X, s, eps, 2, 77, cfg=sng.Config(schedule=schedule))
+        assert_same(gl, gd, ref, "n=%d d=%d schedule=%d" % (n, d, schedule))
+        assert st.accepted == ref.accepted and st.self_pairs == ref.self_pairs
 
 
 @pytest.mark.timeout(600)
