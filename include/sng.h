@@ -153,6 +153,18 @@ int sng_dbscan_lowp(const float *X, int64_t n, int32_t d, int64_t ld, const uint
                     int32_t min_pts, uint64_t seed, int32_t *labels, uint32_t *degrees,
                     void *workspace, size_t ws_bytes, const sng_config *cfg, void *stream);
 
+/* Compact cluster ids. The method defines its clusters up to a renaming
+ * (Section 4.1, Theorem 1); the clustering calls name each cluster by its
+ * root, the smallest core index in it. out[i] = the rank of labels[i] among
+ * the distinct roots in increasing order (clusters 0..k-1), -1 for noise.
+ * labels: device i32 [n] as written by a clustering call (each entry -1 or
+ * the index r of a root, labels[r] == r); any other entry maps to -1.
+ * out: device i32 [n], must not overlap labels (SNG_EINVAL otherwise).
+ * n_clusters: device i32, may be NULL; receives k. No workspace: out holds
+ * the intermediate tile counts. */
+int sng_compact_labels(const int32_t *labels, int64_t n, int32_t *out, int32_t *n_clusters,
+                       void *stream);
+
 /* Post-processing only (Algorithm 1, core points, components and borders) on
  * an explicit list of accepted pairs: edges (device, int32 [n_edges][2]),
  * each pair counted once per occurrence; self-pairs are not allowed.

@@ -188,3 +188,20 @@ def sweep(X: np.ndarray, eps_grid, min_pts_grid, seed: int, s: Optional[float] =
             labels[p, k] = r.labels
             degs[k] = r.deg
     return labels, degs
+
+
+def compact_labels(labels) -> tuple[np.ndarray, int]:
+    """Clusters renamed 0..k-1 in increasing order of their root (the method
+    fixes clusters only up to a renaming: Section 4.1, Theorem 1). A root is
+    an r with labels[r] == r; an entry that is neither -1 nor a root's index
+    becomes -1. Returns (int32 [n], k)."""
+    L = np.asarray(labels, np.int64).ravel()
+    n = L.size
+    idx = np.arange(n)
+    roots = idx[L == idx]  # ascending
+    rank = np.full(n, -1, np.int64)
+    rank[roots] = np.arange(roots.size)
+    out = np.full(n, -1, np.int32)
+    ok = (L >= 0) & (L < n)
+    out[ok] = rank[L[ok]]
+    return out, int(roots.size)

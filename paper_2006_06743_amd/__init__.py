@@ -185,6 +185,23 @@ def graph_labels(n: int, edges: torch.Tensor, min_pts: int, device=None):
     return labels, deg, ws
 
 
+def compact_labels(labels: torch.Tensor, out: Optional[torch.Tensor] = None):
+    """Clusters renumbered 0..k-1 in increasing root order (noise stays -1):
+    returns (out int32 [n], n_clusters int32 [1]), both on the device."""
+    if not labels.is_cuda or labels.dtype != torch.int32 or labels.dim() != 1:
+        raise ValueError("labels must be a 1-D int32 device tensor")
+    lab = labels.contiguous()
+    n = lab.numel()
+    if out is None:
+        out = torch.empty(n, dtype=torch.int32, device=lab.device)
+    k = torch.empty(1, dtype=torch.int32, device=lab.device)
+    check(_lib.load().sng_compact_labels(lab.data_ptr() if n else None, n,
+                                         out.data_ptr() if n else None, k.data_ptr(),
+                                         torch.cuda.current_stream(lab.device).cuda_stream),
+          "sng_compact_labels")
+    return out, k
+
+
 def sweep(X: torch.Tensor, s: float, eps_grid: Sequence[float], min_pts_grid: Sequence[int],
           seed: int, want_degrees: bool = True, ws: Optional[torch.Tensor] = None,
           cfg: Optional[Config] = None):

@@ -457,6 +457,23 @@ int sng_graph_labels(int64_t n, const int32_t *edges, int64_t n_edges, int32_t m
     return SNG_OK;
 }
 
+int sng_compact_labels(const int32_t *labels, int64_t n, int32_t *out, int32_t *n_clusters,
+                       void *stream)
+{
+    if (n < 0 || (n > 0 && (!labels || !out)))
+        return SNG_EINVAL;
+    if (n > kMaxN)
+        return SNG_ERANGE;
+    if (n > 0) {
+        const uintptr_t a0 = (uintptr_t)labels, a1 = a0 + (uintptr_t)n * 4;
+        const uintptr_t b0 = (uintptr_t)out, b1 = b0 + (uintptr_t)n * 4;
+        if (a0 < b1 && b0 < a1)
+            return SNG_EINVAL;  // out must not overlap labels
+    }
+    SNG_TRY(launch_compact(labels, (uint32_t)n, out, n_clusters, (hipStream_t)stream));
+    return SNG_OK;
+}
+
 static size_t sweep_ws_bytes(int64_t n, int64_t m, int32_t K, int32_t P)
 {
     const Sizes z = sizes_for(n, m);

@@ -113,6 +113,8 @@ hipError_t launch_fill_u32(uint32_t *p, uint64_t count, uint32_t v, hipStream_t 
 hipError_t launch_fill_u64(unsigned long long *p, uint64_t count, unsigned long long v,
                            hipStream_t st);
 hipError_t launch_core_init(const Inst &I, hipStream_t st);
+hipError_t launch_compact(const int32_t *labels, uint32_t n, int32_t *out, int32_t *n_clusters,
+                          hipStream_t st);
 hipError_t launch_hook_mask(const Inst &I, hipStream_t st);
 hipError_t launch_finalize(const Inst &I, hipStream_t st);
 hipError_t launch_edge_degrees(const int32_t *edges, int64_t n_edges, uint32_t *deg,

@@ -96,3 +96,10 @@ def test_invalid_arguments_rejected_before_launch(lib):
     assert lib.sng_graph_labels(-1, None, 0, 1, lab, None, ws, 10**9, None) == -1
     assert lib.sng_graph_labels(5, None, 3, 1, lab, None, ws, 10**9, None) == -1
     assert lib.sng_graph_labels(5, fake, 3, 1, lab, None, ws, 1, None) == -3
+    # compaction: null pointers, negative n, overlapping output, oversize n
+    a = ctypes.c_void_p(0x10000)
+    assert lib.sng_compact_labels(None, 5, a, None, None) == -1
+    assert lib.sng_compact_labels(a, 5, None, None, None) == -1
+    assert lib.sng_compact_labels(a, -1, a, None, None) == -1
+    assert lib.sng_compact_labels(a, 5, ctypes.c_void_p(0x10000 + 16), None, None) == -1
+    assert lib.sng_compact_labels(a, 2**31, ctypes.c_void_p(0x10000 + 2**33), None, None) == -2

@@ -222,3 +222,29 @@ def test_cluster_entry_point_many_minpts(sng, orc):
         assert_same(lab.cpu().numpy(), deg.cpu().numpy().view(np.uint32), ref, "MinPts=%d" % mp)
         st = sng.stats(ws)
         assert st.n_core == ref.n_core and st.n_clusters == ref.n_clusters
+
+
+def compact_on_gpu(sng, labels):
+    import torch
+    t = torch.from_numpy(np.ascontiguousarray(labels, np.int32)).cuda()
+    out, k = sng.compact_labels(t)
+    torch.cuda.synchronize()
+    return out.cpu().numpy(), int(k.cpu()[0])
+
+
+@pytest.mark.parametrize("n", [0, 1, 4095, 4096, 4097, 70001])
+def test_compact_labels(sng, orc, n):
+    """sng_compact_labels against the oracle's compaction, on the labels of a
+    real clustering (several 4096-label tiles and a ragged tail) and on
+    labellings dense in roots and in invalid entries."""
+    rng = np.random.default_rng(77 + n)
+    print("compact n", n, flush=True)
+    X = wl.random_instance(rng, n, 2, "blobs", spread=0.03)
+    gl, gd, st = run(sng, X, 0.05, 0.02, 3, int(rng.integers(0, 2**63)))
+    for lab in [gl, np.arange(n, dtype=np.int32),
+                np.where(rng.random(n) < 0.3, -1, rng.integers(-3, n + 3, n)).astype(np.int32)]:
+        got, k = compact_on_gpu(sng, lab)
+        ref, kr = orc.compact_labels(lab)
+        assert k == kr
+        bad = np.nonzero(got != ref)[0]
+        assert bad.size == 0, "%d ids differ (first %s)" % (bad.size, bad[:5])
