@@ -130,12 +130,17 @@ Inst make_inst(const float *X, int64_t n, int32_t d, int64_t ld, int64_t m, doub
     return I;
 }
 
-PassAShape shape_for(const Inst &I, const sng_config *cfg)
+// bucketed: the partner-block schedule, whose evaluate kernel keeps the
+// source row of every record in flight too; it defaults to 4 records in
+// flight per group (fewer registers, twice the waves per SIMD).
+PassAShape shape_for(const Inst &I, const sng_config *cfg, bool bucketed = false)
 {
     const bool vec_ok = ((uintptr_t)I.X % 16 == 0) && (I.ld % 4 == 0);
+    int prefetch = cfg ? cfg->prefetch : 0;
+    if (bucketed && prefetch == 0)
+        prefetch = 4;
     return resolve_shape(I.d, vec_ok, cfg ? cfg->lanes_per_pair : 0,
-                         cfg ? cfg->chunks_per_wave : 0, cfg ? cfg->stage_lds : 0,
-                         cfg ? cfg->prefetch : 0);
+                         cfg ? cfg->chunks_per_wave : 0, cfg ? cfg->stage_lds : 0, prefetch);
 }
 
 int check_cfg(const sng_config *cfg)
@@ -186,9 +191,9 @@ int pick_bucket(const Inst &I, const sng_config *cfg, void *workspace, size_t ws
     if (align_up(used + bucket_bytes(*B)) > ws_bytes)
         return sched == 2 ? SNG_EWORKSPACE : SNG_OK;
     Carve cv((char *)workspace + used);
-    B->rec = cv.take<uint32_t>(B->gen_waves * B->region);
-    B->seg = cv.take<uint32_t>(B->gen_waves * B->NJ * 2);
-    B->start = cv.take<uint32_t>(B->gen_waves * 2);
+    B->rec = cv.take<uint32_t>(B->ranges * B->region);
+    B->seg = cv.take<uint32_t>(B->ranges * B->NJ * 2);
+    B->start = cv.take<uint32_t>(B->ranges * 2);
     B->queue = cv.take<unsigned long long>(kXcds);
     *use = true;
     return SNG_OK;
@@ -207,7 +212,7 @@ int run_plain(Inst &I, const sng_config *cfg, bool labels_wanted, const BucketGe
     SNG_TRY(launch_fill_u32(I.deg, I.n, 0u, st));
     if (I.m > 0 && B) {
         SNG_TRY(launch_fill_u32(I.mask, I.chunks * 8, 0u, st));
-        SNG_TRY(launch_bucket_plain(I, *B, shape_for(I, cfg), st));
+        SNG_TRY(launch_bucket_plain(I, *B, shape_for(I, cfg, true), st));
     } else if (I.m > 0) {
         SNG_TRY(launch_pass_a(I, shape_for(I, cfg), st));
     }
@@ -553,7 +558,7 @@ int sng_dbscan_sweep(const float *X, int64_t n, int32_t d, int64_t ld, double s,
     if ((rc = pick_bucket(I, cfg, workspace, ws_bytes, cv.off, &B, &use))) return rc;
     SNG_TRY(init_header(I.cnt, (uint64_t)n * (uint64_t)m, band, st));
     SNG_TRY(launch_fill_u32(S.hist, (uint64_t)n * n_eps, 0u, st));
-    SNG_TRY(launch_sweep(I, S, shape_for(I, cfg), use ? &B : nullptr, st));
+    SNG_TRY(launch_sweep(I, S, shape_for(I, cfg, use), use ? &B : nullptr, st));
     return SNG_OK;
 }
 

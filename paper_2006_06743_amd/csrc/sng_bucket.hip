@@ -5,11 +5,13 @@
 // rest of the line, and none is reused. This schedule first sorts the slots
 // by partner block and then evaluates them block by block:
 //
-//   generate  one wavefront per range of kGenCalls Philox calls. It counts
-//             its non-self slots per partner block (2^bshift rows, about half
-//             a MB of X), then regenerates them and writes 4-byte records
-//             (call offset in its range, word, partner offset in the block)
-//             into one segment per block of its private region;
+//   generate  one workgroup per range of kRangeCalls Philox calls. Each
+//             non-self slot becomes a 4-byte record (call offset in the
+//             range, word, partner offset in its partner block of 2^bshift
+//             rows, about half a MB of X). The workgroup counting-sorts its
+//             records by partner block in LDS and copies them out in order,
+//             so its region of the record array is written with contiguous
+//             stores, one segment per partner block;
 //   evaluate  partner blocks are dealt to the eight XCDs (block J to XCD
 //             J mod 8; workgroup b runs on XCD b mod 8). The wavefronts of
 //             one XCD take the segments of its blocks in block-major order
@@ -26,7 +28,6 @@
 namespace sng {
 
 constexpr uint32_t kRecOffShift = 18;  // record: call offset (14 bits) | word (2) | partner (16)
-constexpr uint64_t kTicket = 4;        // consecutive segments taken per queue atomic
 
 struct BucketPlainPolicy {
     uint32_t *deg;
@@ -102,141 +103,233 @@ struct BucketSweepPolicy {
 };
 
 // ---------------------------------------------------------------------------
-// Generate: count per partner block, prefix, regenerate and scatter records.
-// LDS: two counters per block for each of the 4 wavefronts.
+// Generate. LDS: the record stage of the range, then counts and offsets per
+// partner block.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_bkt_generate(Inst I, BucketGeom B)
+constexpr uint32_t kGenThreads = 1024;
+constexpr uint32_t kCallsPerThread = (uint32_t)kRangeCalls / kGenThreads;
+constexpr uint32_t kRangeSlots = 4 * (uint32_t)kRangeCalls;
+static_assert(kCallsPerThread * kGenThreads == kRangeCalls, "range split");
+static_assert(kRangeCalls <= (1u << (32 - kRecOffShift)), "call offset field");
+static_assert(kMaxPartnerBlocks <= kGenThreads, "one count per thread in the prefix");
+
+// Exclusive prefix of v over a workgroup of kGenThreads threads; *total gets
+// the sum. wsum: kGenThreads / kWave words of LDS.
+__device__ __forceinline__ uint32_t gen_exclusive(uint32_t v, uint32_t *wsum, uint32_t *total)
+{
+    const int lane = lane_id();
+    const int w = threadIdx.x / kWave;
+    uint32_t x = v;
+#pragma unroll
+    for (int s = 1; s < kWave; s <<= 1) {
+        const uint32_t u = __shfl_up(x, s);
+        if (lane >= s)
+            x += u;
+    }
+    if (lane == kWave - 1)
+        wsum[w] = x;
+    __syncthreads();
+    uint32_t before = 0, all = 0;
+#pragma unroll
+    for (int k = 0; k < (int)(kGenThreads / kWave); ++k) {
+        const uint32_t s = wsum[k];
+        before += (k < w) ? s : 0u;
+        all += s;
+    }
+    *total = all;
+    return before + x - v;
+}
+
+__global__ __launch_bounds__(kGenThreads) void k_bkt_generate(Inst I, BucketGeom B)
 {
     extern __shared__ uint32_t lds_u32[];
-    const int lane = lane_id();
-    const int wib = threadIdx.x / kWave;
-    uint32_t *cnt = lds_u32 + (size_t)wib * 2 * B.NJ;
-    uint32_t *cur = cnt + B.NJ;
-    const uint64_t gw = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    __shared__ uint32_t wsum[kGenThreads / kWave];
+    uint32_t *stage = lds_u32;              // [kRangeSlots]
+    uint32_t *cnt = lds_u32 + kRangeSlots;  // [NJ]
+    uint32_t *pre = cnt + B.NJ;             // [NJ]
+    const uint32_t tid = threadIdx.x;
+    const uint64_t r = blockIdx.x;
+    const uint64_t call_lo = r * kRangeCalls;
+    const uint64_t call_hi = min(call_lo + kRangeCalls, I.calls);
+    const uint32_t i0 = (uint32_t)(call_lo / I.C);
+    const uint32_t c0 = (uint32_t)(call_lo - (uint64_t)i0 * I.C);
+    for (uint32_t k = tid; k < B.NJ; k += kGenThreads)
+        cnt[k] = 0;
+    if (tid == 0) {
+        B.start[2 * r + 0] = i0;  // source and call of the range's first call
+        B.start[2 * r + 1] = c0;
+    }
+    __syncthreads();
+    // key: partner block << 16 | rank of the record within its block
+    uint32_t key[4 * kCallsPerThread], rec[4 * kCallsPerThread];
     uint32_t self = 0;
-    if (gw < B.gen_waves) {  // wave-uniform
-        for (uint32_t k = lane; k < B.NJ; k += kWave)
-            cnt[k] = 0;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        const uint64_t call_lo = gw * kGenCalls;
-        const uint64_t call_hi = min(call_lo + kGenCalls, I.calls);
-        const uint32_t i0 = (uint32_t)(call_lo / I.C);
-        const uint32_t c0 = (uint32_t)(call_lo - (uint64_t)i0 * I.C);
-        if (lane == 0) {
-            B.start[2 * gw + 0] = i0;  // source and call of the range's first call
-            B.start[2 * gw + 1] = c0;
-        }
-        for (int pass = 0; pass < 2; ++pass) {
-            for (uint64_t base = call_lo; base < call_hi; base += kWave) {
-                const uint32_t off = (uint32_t)(base - call_lo) + (uint32_t)lane;
-                const bool live = base + lane < call_hi;
-                uint32_t cc = c0 + off, ii = i0;
-                if (cc >= I.C) {
-                    const uint32_t q = div_exact(cc, I.C, I.inv_C);
-                    ii += q;
-                    cc -= q * I.C;
-                }
-                const uint32_t nvalid = live ? min(4u, I.m - 4u * cc) : 0u;
-                const Words4 W = philox10(cc, ii, I.key0, I.key1);
 #pragma unroll
-                for (int w = 0; w < 4; ++w) {
-                    if ((uint32_t)w < nvalid) {
-                        const uint32_t j = mod_exact(W.w[w], I.n, I.inv_n);
-                        if (j == ii) {
-                            self += (pass == 0);
-                        } else {
-                            const uint32_t J = j >> B.bshift;
-                            if (pass == 0) {
-                                atomicAdd(cnt + J, 1u);
-                            } else {
-                                const uint32_t pos = atomicAdd(cur + J, 1u);
-                                B.rec[gw * B.region + pos] = (off << kRecOffShift) |
-                                                             ((uint32_t)w << 16) |
-                                                             (j & ((1u << B.bshift) - 1u));
-                            }
-                        }
-                    }
+    for (uint32_t c = 0; c < kCallsPerThread; ++c) {
+        const uint32_t off = c * kGenThreads + tid;
+        const bool live = call_lo + off < call_hi;
+        uint32_t cc = c0 + off, ii = i0;
+        if (cc >= I.C) {
+            const uint32_t q = div_exact(cc, I.C, I.inv_C);
+            ii += q;
+            cc -= q * I.C;
+        }
+        const uint32_t nvalid = live ? min(4u, I.m - 4u * cc) : 0u;
+        const Words4 W = philox10(cc, ii, I.key0, I.key1);
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+            uint32_t kk = ~0u, rr = 0;
+            if ((uint32_t)w < nvalid) {
+                const uint32_t j = mod_exact(W.w[w], I.n, I.inv_n);
+                if (j == ii) {
+                    ++self;
+                } else {
+                    const uint32_t J = j >> B.bshift;
+                    kk = (J << 16) | atomicAdd(cnt + J, 1u);
+                    rr = (off << kRecOffShift) | ((uint32_t)w << 16) |
+                         (j & ((1u << B.bshift) - 1u));
                 }
             }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            if (pass == 0) {
-                // exclusive prefix of the block counts (lane 0; NJ <= 1024)
-                if (lane == 0) {
-                    uint32_t run = 0;
-                    for (uint32_t k = 0; k < B.NJ; ++k) {
-                        const uint32_t c = cnt[k];
-                        B.seg[(gw * B.NJ + k) * 2 + 0] = run;
-                        B.seg[(gw * B.NJ + k) * 2 + 1] = c;
-                        cur[k] = run;
-                        run += c;
-                    }
-                }
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            }
+            key[4 * c + w] = kk;
+            rec[4 * c + w] = rr;
+        }
+    }
+    __syncthreads();
+    const uint32_t v = tid < B.NJ ? cnt[tid] : 0u;
+    uint32_t total;
+    const uint32_t ex = gen_exclusive(v, wsum, &total);
+    if (tid < B.NJ) {
+        pre[tid] = ex;
+        B.seg[(r * B.NJ + tid) * 2 + 0] = ex;
+        B.seg[(r * B.NJ + tid) * 2 + 1] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (uint32_t k = 0; k < 4 * kCallsPerThread; ++k) {
+        if (key[k] != ~0u)
+            stage[pre[key[k] >> 16] + (key[k] & 0xFFFFu)] = rec[k];
+    }
+    __syncthreads();
+    uint32_t *dst = B.rec + r * B.region;
+    for (uint32_t k = 4 * tid; k < total; k += 4 * kGenThreads) {
+        if (k + 4 <= total) {
+            *reinterpret_cast<uint4 *>(dst + k) = *reinterpret_cast<const uint4 *>(stage + k);
+        } else {
+            for (uint32_t e = k; e < total; ++e)
+                dst[e] = stage[e];
         }
     }
     const int slots[1] = {kCntSelf};
-    const uint32_t v[1] = {self};
-    block_count_add<1>(I.cnt, slots, v);
+    const uint32_t sv[1] = {self};
+    block_count_add<1>(I.cnt, slots, sv);
 }
 
 // ---------------------------------------------------------------------------
 // Evaluate.
 // ---------------------------------------------------------------------------
-// One segment: the groups of the wave take its records interleaved (record
-// r goes to group r mod kGroups), so every record load is one coalesced read
-// of consecutive records; the source and partner rows of P records per group
-// are fetched together, then decided one by one.
+// One work item (ticket): the segments of partner block J from kTicketRanges
+// consecutive generator ranges, walked as one sequence of records f =
+// 0..total-1. Lane l < T holds the segment of range r0 + l (its record base,
+// first record index in the sequence, and first source and call). The groups
+// of the wave take the records interleaved (record f goes to group f mod
+// kGroups), so every record load is a coalesced read; a window of P*kGroups
+// records meets only a few segments, found with wave-wide ballots and
+// scalar reads of those segments' entries. Records of the next window are
+// loaded while the current one is decided.
+constexpr uint32_t kTicketRanges = 16;
+static_assert(kTicketRanges <= kWave, "one lane per segment of a ticket");
+
+__device__ __forceinline__ uint64_t readlane_u64(uint64_t v, int l)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), l);
+    return ((uint64_t)hi << 32) | lo;
+}
+
 template <class Row, int OB, class Pol>
-__device__ __forceinline__ void eval_segment(const Inst &I, const BucketGeom &B, Pol &pol,
-                                             uint64_t gw, uint32_t J, Tally &tally)
+__device__ __forceinline__ void eval_ticket(const Inst &I, const BucketGeom &B, Pol &pol,
+                                            uint64_t r0, uint32_t T, uint32_t J, Tally &tally)
 {
     constexpr int G = Row::kG;
     constexpr int P = 4 * OB;  // records in flight per group
     constexpr int kGroups = kWave / G;
+    constexpr uint32_t kStep = (uint32_t)P * kGroups;
     const int lane = lane_id();
     const int q = lane & (G - 1);
     const int grp = lane / G;
-    const uint32_t off = B.seg[(gw * B.NJ + J) * 2 + 0];
-    const uint32_t cnt = B.seg[(gw * B.NJ + J) * 2 + 1];
-    if (cnt == 0)
-        return;
-    const uint32_t *rec = B.rec + gw * B.region + off;
-    const uint64_t call_lo = gw * kGenCalls;
-    const uint32_t i0 = B.start[2 * gw + 0];
-    const uint32_t c0 = B.start[2 * gw + 1];
+    uint32_t cnt_l = 0, i0_l = 0, c0_l = 0;
+    uint64_t base_l = 0;
+    if ((uint32_t)lane < T) {
+        const uint64_t r = r0 + (uint64_t)lane;
+        base_l = r * B.region + B.seg[(r * B.NJ + J) * 2 + 0];
+        cnt_l = B.seg[(r * B.NJ + J) * 2 + 1];
+        i0_l = B.start[2 * r + 0];
+        c0_l = B.start[2 * r + 1];
+    }
+    uint32_t incl = cnt_l;
+#pragma unroll
+    for (int s = 1; s < kWave; s <<= 1) {
+        const uint32_t u = __shfl_up(incl, s);
+        if (lane >= s)
+            incl += u;
+    }
+    const uint32_t excl_l = incl - cnt_l;  // non-decreasing over the lanes
+    const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)incl, kWave - 1);
+    if (total == 0)
+        return;  // wave-uniform
+    base_l -= excl_l;  // record f of segment l is B.rec[base_l + f]
+
+    // Loads the records of window [f0, f0 + kStep) and their segments.
+    auto locate = [&](uint32_t f0, uint32_t (&vv)[P], uint32_t (&ss)[P]) {
+        const int s_lo = __popcll(__ballot(excl_l <= f0)) - 1;
+        const int s_hi = min(__popcll(__ballot(excl_l < f0 + kStep)), (int)T) - 1;
+        uint64_t bk[P];
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            bk[k] = readlane_u64(base_l, s_lo);
+            ss[k] = (uint32_t)s_lo;
+        }
+        for (int b = s_lo + 1; b <= s_hi; ++b) {  // wave-uniform
+            const uint32_t e = (uint32_t)__builtin_amdgcn_readlane((int)excl_l, b);
+            const uint64_t bb = readlane_u64(base_l, b);
+#pragma unroll
+            for (int k = 0; k < P; ++k) {
+                if (f0 + (uint32_t)(k * kGroups + grp) >= e) {
+                    bk[k] = bb;
+                    ss[k] = (uint32_t)b;
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            const uint32_t f = f0 + (uint32_t)(k * kGroups + grp);
+            vv[k] = (f < total) ? B.rec[bk[k] + f] : 0u;
+        }
+    };
+
     const uint32_t jbase = J << B.bshift;
     const float *__restrict__ X = I.X;
     const int64_t ld = I.ld;
     const int d = I.d;
-    constexpr uint32_t kStep = (uint32_t)P * kGroups;
-    uint32_t nxt[P];
-#pragma unroll
-    for (int k = 0; k < P; ++k) {
-        const uint32_t r = k * kGroups + grp;
-        nxt[k] = (r < cnt) ? rec[r] : 0u;
-    }
-    for (uint32_t r0 = 0; r0 < cnt; r0 += kStep) {  // wave-uniform
-        uint32_t v[P];
+    uint32_t nv[P], ns[P];
+    locate(0, nv, ns);
+    for (uint32_t f0 = 0; f0 < total; f0 += kStep) {  // wave-uniform
+        uint32_t v[P], sv[P];
 #pragma unroll
         for (int k = 0; k < P; ++k) {
-            v[k] = nxt[k];
-            const uint32_t r = r0 + kStep + k * kGroups + grp;
-            nxt[k] = (r < cnt) ? rec[r] : 0u;
+            v[k] = nv[k];
+            sv[k] = ns[k];
         }
+        if (f0 + kStep < total)
+            locate(f0 + kStep, nv, ns);
         uint32_t ii[P], cj[P], ww[P];
         uint64_t call[P];
         bool live[P];
         typename Row::Buf bi[P], bj[P];
 #pragma unroll
         for (int k = 0; k < P; ++k) {
-            live[k] = r0 + k * kGroups + grp < cnt;  // group-uniform
+            live[k] = f0 + (uint32_t)(k * kGroups + grp) < total;  // group-uniform
+            const uint32_t i0 = (uint32_t)__shfl((int)i0_l, (int)sv[k]);
+            const uint32_t c0 = (uint32_t)__shfl((int)c0_l, (int)sv[k]);
             const uint32_t co = v[k] >> kRecOffShift;
             ww[k] = (v[k] >> 16) & 3u;
             cj[k] = jbase | (v[k] & 0xFFFFu);
@@ -247,7 +340,7 @@ __device__ __forceinline__ void eval_segment(const Inst &I, const BucketGeom &B,
                 cc -= qq * I.C;
             }
             ii[k] = i;
-            call[k] = call_lo + co;
+            call[k] = (r0 + sv[k]) * kRangeCalls + co;
             const uint32_t sj = live[k] ? cj[k] : 0u;  // row 0 always exists
             const uint32_t si = live[k] ? i : 0u;
             bj[k] = Row::fetch(X + (int64_t)sj * ld, q, d);
@@ -273,34 +366,33 @@ __device__ __forceinline__ uint32_t my_xcd()
 }
 
 // Each XCD owns the partner blocks J = x, x + kXcds, ... and a queue over
-// (J, generator range) in block-major order: all wavefronts of the XCD work
-// on one partner block at a time (kept in that XCD's L2) while the source
-// rows stream in small sequential pieces. Wavefronts take kTicket
-// consecutive segments per queue atomic, then help the other queues until
-// all are empty, so every segment is taken exactly once whichever XCDs the
+// (J, ticket) in block-major order: all wavefronts of the XCD work on one
+// partner block at a time (kept in that XCD's L2) while the source rows
+// stream in sequential pieces. Wavefronts then help the other queues until
+// all are empty, so every ticket is taken exactly once whichever XCDs the
 // workgroups land on.
 template <class Row, int OB, class Pol>
 __device__ __forceinline__ void eval_all(const Inst &I, const BucketGeom &B, Pol &pol,
                                          Tally &tally)
 {
     const uint32_t home = my_xcd();
+    const uint64_t tpj = (B.ranges + kTicketRanges - 1) / kTicketRanges;  // tickets per block
     for (uint32_t s = 0; s < kXcds; ++s) {
         const uint32_t x = (home + s) % kXcds;
         const uint64_t blocks = (B.NJ > x) ? (B.NJ - x + kXcds - 1) / kXcds : 0;
-        const uint64_t total = blocks * B.gen_waves;
+        const uint64_t total = blocks * tpj;
         for (;;) {
-            unsigned long long e0 = 0;
+            unsigned long long e = 0;
             if (lane_id() == 0)
-                e0 = atomicAdd(B.queue + x, (unsigned long long)kTicket);
-            e0 = __shfl(e0, 0);
-            if (e0 >= total)
+                e = atomicAdd(B.queue + x, 1ull);
+            e = __shfl(e, 0);
+            if (e >= total)
                 break;  // wave-uniform
-            const uint64_t e1 = min(e0 + kTicket, total);
-            for (uint64_t e = e0; e < e1; ++e) {
-                const uint64_t jl = e / B.gen_waves;
-                const uint64_t gw = e - jl * B.gen_waves;
-                eval_segment<Row, OB>(I, B, pol, gw, (uint32_t)(x + jl * kXcds), tally);
-            }
+            const uint64_t jl = e / tpj;
+            const uint64_t r0 = (e - jl * tpj) * kTicketRanges;
+            const uint64_t left = B.ranges - r0;
+            const uint32_t T = (uint32_t)(left < kTicketRanges ? left : kTicketRanges);
+            eval_ticket<Row, OB>(I, B, pol, r0, T, (uint32_t)(x + jl * kXcds), tally);
         }
     }
 }
@@ -366,8 +458,8 @@ bool bucket_geometry(int64_t n, int d, int64_t m, bool force, BucketGeom *g)
         return false;
     const uint64_t C = (uint64_t)((m + 3) / 4);
     const uint64_t calls = (uint64_t)n * C;
-    b.gen_waves = (calls + kGenCalls - 1) / kGenCalls;
-    b.region = kGenCalls * 4;
+    b.ranges = (calls + kRangeCalls - 1) / kRangeCalls;
+    b.region = kRangeSlots;
     if (g)
         *g = b;
     return true;
@@ -375,8 +467,8 @@ bool bucket_geometry(int64_t n, int d, int64_t m, bool force, BucketGeom *g)
 
 size_t bucket_bytes(const BucketGeom &g)
 {
-    return (size_t)g.gen_waves * g.region * 4 + (size_t)g.gen_waves * g.NJ * 8 +
-           (size_t)g.gen_waves * 8 + kXcds * 8 + 1280;
+    return (size_t)g.ranges * g.region * 4 + (size_t)g.ranges * g.NJ * 8 +
+           (size_t)g.ranges * 8 + kXcds * 8 + 1280;
 }
 
 static hipError_t generate(const Inst &I, const BucketGeom &B, hipStream_t st)
@@ -384,11 +476,10 @@ static hipError_t generate(const Inst &I, const BucketGeom &B, hipStream_t st)
     hipError_t e0 = launch_fill_u64(B.queue, kXcds, 0ull, st);
     if (e0 != hipSuccess)
         return e0;
-    const uint64_t blocks = (B.gen_waves + 3) / 4;
-    if (blocks > 0x7FFFFFFFull)
+    if (B.ranges > 0x7FFFFFFFull || B.NJ > kMaxPartnerBlocks)
         return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_bkt_generate, dim3((unsigned)blocks), dim3(256),
-                       (size_t)B.NJ * 2 * 4 * sizeof(uint32_t), st, I, B);
+    hipLaunchKernelGGL(k_bkt_generate, dim3((unsigned)B.ranges), dim3(kGenThreads),
+                       ((size_t)kRangeSlots + 2 * (size_t)B.NJ) * sizeof(uint32_t), st, I, B);
     return hipGetLastError();
 }
 

@@ -77,16 +77,16 @@ hipError_t launch_batch(const Inst *T, const BatchGeom &G, int d, bool vec_ok,
 
 // L2-reuse schedule of the sampled-distance pass (sng_bucket.hip).
 constexpr int kXcds = 8;                    // workgroup b runs on XCD b mod 8
-constexpr uint64_t kGenCalls = 16384;       // Philox calls per generator wavefront
+constexpr uint64_t kRangeCalls = 8192;      // Philox calls per generator range (one workgroup)
 constexpr uint32_t kMaxPartnerBlocks = 1024;
 struct BucketGeom {
     uint32_t bshift;     // partner block = 2^bshift rows
     uint32_t NJ;         // partner blocks
-    uint64_t gen_waves;  // generator ranges
+    uint64_t ranges;     // generator ranges
     uint64_t region;     // records per generator range (capacity)
-    uint32_t *rec;       // [gen_waves][region] 4-byte slot records
-    uint32_t *seg;       // [gen_waves][NJ][2] segment offset and count
-    uint32_t *start;     // [gen_waves][2] source and call of each range's first call
+    uint32_t *rec;       // [ranges][region] 4-byte slot records
+    uint32_t *seg;       // [ranges][NJ][2] segment offset and count
+    uint32_t *start;     // [ranges][2] source and call of each range's first call
     unsigned long long *queue;  // [kXcds] next segment of each XCD's queue
 };
 bool bucket_geometry(int64_t n, int d, int64_t m, bool force, BucketGeom *g);
