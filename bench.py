@@ -1,14 +1,16 @@
 #!/usr/bin/env python3
 """SNG-DBSCAN benchmark on one MI355X.
 
-One step is one pass of the whole method (sampled-distance pass, core mask,
-hook, finalize) over the 1e6 x 16 Gaussian-mixture workload (s=0.001,
-eps=2.0, MinPts=5, seed 2) with X already resident in HBM. Prints one JSON
-line with pair evaluations per second (whole job), the roofline of the
-sampled-distance kernel, the oracle's CPU rate on a bounded sample, and the
-plain-vs-mixed / plain-vs-batched comparisons.
+One step is one pass of the whole method over the 1e6 x 16 Gaussian-mixture
+workload (s=0.001, eps=2.0, MinPts=5, seed 2) with X already resident in HBM:
+draw the sample (partners sorted by partner block), evaluate it (distances,
+degrees, accept bits), then core mask, hook and finalize. Prints one JSON line
+with pair evaluations per second (whole job), the roofline of the evaluate
+kernel, the oracle's CPU rate on a bounded sample, and the plain-vs-mixed,
+plain-vs-sweep and sequential-vs-batched comparisons.
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-forms] [--no-cpu-baseline]
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--schedule auto|direct]
+                    [--no-forms] [--no-cpu-baseline] [--calibrate-copy]
 """
 import argparse
 import hashlib
@@ -22,29 +24,39 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "sampled pair-distance evals/sec + end-to-end cluster time (plain vs mixed/batched)"
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pass_a_gmm16d_traffic.json")
-PASS_A_SOURCES = ["paper_2006_06743_amd/csrc/sng_pass_a.hip",
-                  "paper_2006_06743_amd/csrc/sng_pass_a.hpp",
-                  "paper_2006_06743_amd/csrc/sng_device.hpp"]
+# dominant kernel of each schedule: its name, the sources it is built from,
+# and the committed counter summary of its HBM traffic on this workload
+KERNELS = {
+    "partner": {"name": "k_bkt_eval_plain (partner-block evaluate)",
+                "traffic": os.path.join(ROOT, "profiles", "bkt_eval_gmm16d_traffic.json"),
+                "sources": ["paper_2006_06743_amd/csrc/sng_bucket.hip",
+                            "paper_2006_06743_amd/csrc/sng_pass_a.hpp",
+                            "paper_2006_06743_amd/csrc/sng_device.hpp"]},
+    "direct": {"name": "k_pass_a (direct-gather sampled-distance pass)",
+               "traffic": os.path.join(ROOT, "profiles", "pass_a_gmm16d_traffic.json"),
+               "sources": ["paper_2006_06743_amd/csrc/sng_pass_a.hip",
+                           "paper_2006_06743_amd/csrc/sng_pass_a.hpp",
+                           "paper_2006_06743_amd/csrc/sng_device.hpp"]},
+}
 
 
-def kernel_source_sha() -> str:
+def kernel_source_sha(sources) -> str:
     h = hashlib.sha256()
-    for p in PASS_A_SOURCES:
+    for p in sources:
         with open(os.path.join(ROOT, p), "rb") as f:
             h.update(f.read())
     return h.hexdigest()
 
 
-def measured_traffic():
-    """HBM bytes per launch of the sampled-distance kernel from the committed
+def measured_traffic(kern):
+    """HBM bytes per launch of the dominant kernel from the committed
     rocprofv3 counter runs, or None when the kernel changed since."""
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(kern["traffic"]) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
-    if t.get("kernel_source_sha") != kernel_source_sha():
+    if t.get("kernel_source_sha") != kernel_source_sha(kern["sources"]):
         return None
     return float(t["traffic_bytes_per_launch"])
 
@@ -182,6 +194,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--schedule", choices=["auto", "direct"], default="auto",
+                    help="auto: partner-block schedule where it applies (it does here)")
     ap.add_argument("--no-forms", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -202,12 +216,24 @@ def main():
     m = sng.samples_per_point(W.s, W.n)
     slots = W.n * m
     X = torch.from_numpy(W.X).cuda()
-    deg, ws = sng.degrees(X, m, W.eps, W.seed)
+    ws = torch.empty(sng.workspace_size(W.n, W.d, m), dtype=torch.uint8, device="cuda")
+    partner = args.schedule == "auto"
+    if partner:
+        try:
+            sng.sample(W.n, W.d, m, W.seed, ws)
+        except sng.SNGError:
+            partner = False  # the partner-block schedule does not cover this shape
+    eval_cfg = sng.Config(reuse_sample=1) if partner else sng.Config(schedule=1)
+    kern = KERNELS["partner" if partner else "direct"]
+    deg, _ = sng.degrees(X, m, W.eps, W.seed, cfg=eval_cfg, ws=ws)
     labels = sng.cluster(X, m, W.eps, W.seed, W.min_pts, deg, ws)
 
     def step(tm=None):
         if tm: tm.mark()
-        sng.degrees(X, m, W.eps, W.seed, out=deg, ws=ws)
+        if partner:
+            sng.sample(W.n, W.d, m, W.seed, ws)
+        if tm: tm.mark()
+        sng.degrees(X, m, W.eps, W.seed, cfg=eval_cfg, out=deg, ws=ws)
         if tm: tm.mark()
         sng.cluster(X, m, W.eps, W.seed, W.min_pts, deg, ws, labels=labels)
         if tm: tm.mark()
@@ -223,17 +249,23 @@ def main():
     wall = time.perf_counter() - t0
     ms_per_step = wall * 1e3 / args.steps
     ev = tm.ev
-    pass_a = [ev[3 * k].elapsed_time(ev[3 * k + 1]) for k in range(args.steps)]
-    post = [ev[3 * k + 1].elapsed_time(ev[3 * k + 2]) for k in range(args.steps)]
-    pass_a_ms = sum(pass_a) / len(pass_a)
+    span = lambda a: sum(ev[4 * k + a].elapsed_time(ev[4 * k + a + 1])
+                         for k in range(args.steps)) / args.steps
+    sample_ms, eval_ms, post_ms = span(0), span(1), span(2)
     st = sng.stats(ws)
+    if st.overflow:
+        raise SystemExit("bench.py: the evaluate step reported a missing sample")
 
     alg_bytes = slots * W.d * 4  # one gathered row of X per sample slot
-    achieved = alg_bytes / (pass_a_ms * 1e-3) / 1e9
+    achieved = alg_bytes / (eval_ms * 1e-3) / 1e9
+    pass_gbs = alg_bytes / ((sample_ms + eval_ms) * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
-                "kernel": "k_pass_a (sampled-distance pass)", "algorithmic_bytes": alg_bytes,
-                "avg_launch_ms": pass_a_ms}
+                "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(kern),
+                "kernel": kern["name"], "algorithmic_bytes": alg_bytes,
+                "avg_launch_ms": eval_ms,
+                "whole_pass": {"kernels": "sample + evaluate" if partner else "evaluate",
+                               "ms": sample_ms + eval_ms, "achieved": pass_gbs,
+                               "frac": pass_gbs / HBM_PEAK_GBS}}
 
     out = {
         "metric": METRIC,
@@ -252,8 +284,9 @@ def main():
                    "n": W.n, "d": W.d, "s": W.s, "m": m, "eps": W.eps, "min_pts": W.min_pts,
                    "seed": W.seed, "parallelism": "single GPU"},
         "end_to_end_ms": ms_per_step,
-        "pass_ms": {"sampled_distance": pass_a_ms, "core_hook_finalize": sum(post) / len(post)},
-        "sampled_distance_evals_per_s": slots / (pass_a_ms * 1e-3),
+        "pass_ms": {"sample": sample_ms, "evaluate": eval_ms, "core_hook_finalize": post_ms},
+        "schedule": "partner blocks" if partner else "direct gathers",
+        "sampled_distance_evals_per_s": slots / ((sample_ms + eval_ms) * 1e-3),
         "stats": {"slots": st.slots, "self_pairs": st.self_pairs, "accepted": st.accepted,
                   "rechecked": st.rechecked, "n_core": st.n_core, "n_clusters": st.n_clusters,
                   "n_noise": st.n_noise},

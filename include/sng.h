@@ -81,6 +81,7 @@ typedef struct {
     int32_t stage_lds;       /* 1: keep the source row in LDS instead of VGPRs */
     int32_t prefetch;        /* partner rows a group gathers ahead: 4, 8 or 16 */
     int32_t schedule;        /* 0 auto, 1 direct gathers, 2 partner-block (L2 reuse) */
+    int32_t reuse_sample;    /* 1: evaluate the sample sng_sample left in the workspace */
 } sng_config;
 /* schedule: the partner-block form sorts the sample slots by partner block
  * before gathering, so rows narrower than a 128-byte line are reused from
@@ -88,7 +89,14 @@ typedef struct {
  * largest power of two of rows, at most 2^16, whose d*4-byte rows fit in
  * 512 KB (so n <= 2^25 at d = 3, n <= 2^23 at d = 16); auto picks
  * it for d < 32 when X (n*d*4 bytes) exceeds 8 MB and the workspace holds
- * its records, direct gathers otherwise. stage_lds implies direct gathers. */
+ * its records, direct gathers otherwise. stage_lds implies direct gathers.
+ * reuse_sample (sng_degrees and sng_dbscan only; SNG_EINVAL elsewhere and
+ * with schedule 1 or stage_lds): skip drawing the partners and evaluate the
+ * partner-block sample already in the workspace, as left by sng_sample or by
+ * an earlier partner-block call with the same n, d, m and seed (any X of
+ * that shape, any eps). The kernels check a tag stored with the sample; a
+ * missing or different sample does no work and makes sng_stats_read report
+ * SNG_EOVERFLOW. */
 
 /* Flag for sng_workspace_size: size for the direct schedule only (smaller;
  * a workspace of that size makes the automatic schedule choose it). */
@@ -103,7 +111,8 @@ typedef struct {
     uint64_t n_core;
     uint64_t n_clusters;
     uint64_t n_noise;
-    uint64_t overflow;   /* non-zero: a recheck queue overflowed (results invalid) */
+    uint64_t overflow;   /* non-zero: a recheck queue overflowed, or a reused sample was
+                            missing (results invalid) */
     double band_rel;     /* relative half-width of the recheck band used */
 } sng_stats;
 
@@ -126,6 +135,17 @@ int sng_workspace_size(int64_t n, int32_t d, int64_t m, int32_t prec, size_t *by
 int sng_degrees(const float *X, int64_t n, int32_t d, int64_t ld, int64_t m, double eps,
                 uint64_t seed, uint32_t *degrees, void *workspace, size_t ws_bytes,
                 const sng_config *cfg, void *stream);
+
+/* Sampling step alone (Algorithm 1: each point draws its partners): draws
+ * the partner of every sample slot with the partner-block schedule and keeps
+ * the slots, sorted by partner block, in the workspace (sized by
+ * sng_workspace_size for these n, d, m without SNG_WS_DIRECT). Needs no
+ * X: the sample depends on n, d (the block size), m and seed only. Evaluate
+ * it with sng_degrees or sng_dbscan and cfg->reuse_sample = 1, as often as
+ * wanted. SNG_ENOTIMPL where the partner-block schedule does not apply
+ * (d > 32, too many partner blocks). n = 0 or m = 0 is a no-op. */
+int sng_sample(int64_t n, int32_t d, int64_t m, uint64_t seed, void *workspace, size_t ws_bytes,
+               void *stream);
 
 /* Post-processing (Algorithm 1: core points, components of the core
  * subgraph, border assignment) continuing from the accept bits that the last

@@ -17,7 +17,8 @@ import torch
 from . import _lib
 from ._lib import SNG_BF16, SNG_FP16, SNG_FP32, SNGError, check, sng_config, sng_stats
 
-__all__ = ["dbscan", "dbscan_lowp", "degrees", "cluster", "graph_labels", "sweep", "batch", "BatchPlan",
+__all__ = ["dbscan", "dbscan_lowp", "degrees", "sample", "cluster", "compact_labels",
+           "graph_labels", "sweep", "batch", "BatchPlan",
            "samples_per_point", "Config", "Stats", "SNGError", "SNG_FP32", "SNG_BF16",
            "SNG_FP16", "load"]
 
@@ -34,10 +35,12 @@ class Config:
     stage_lds: int = 0
     prefetch: int = 0
     schedule: int = 0  # 0 auto, 1 direct gathers, 2 partner-block (L2 reuse)
+    reuse_sample: int = 0  # 1: evaluate the sample that sample() left in the workspace
 
     def c(self):
         return ctypes.byref(sng_config(self.lanes_per_pair, self.chunks_per_wave,
-                                       self.stage_lds, self.prefetch, self.schedule))
+                                       self.stage_lds, self.prefetch, self.schedule,
+                                       self.reuse_sample))
 
 
 @dataclass
@@ -112,6 +115,15 @@ def degrees(X: torch.Tensor, m: int, eps: float, seed: int, cfg: Optional[Config
                                   out.data_ptr(), ws.data_ptr(), ws.numel(), _cfg(cfg),
                                   _stream(X)), "sng_degrees")
     return out, ws
+
+
+def sample(n: int, d: int, m: int, seed: int, ws: torch.Tensor):
+    """Sampling step alone: draws every slot's partner and keeps the slots
+    sorted by partner block in ws, for degrees()/dbscan() calls with
+    Config(reuse_sample=1). ws: a workspace of workspace_size(n, d, m)."""
+    check(_lib.load().sng_sample(int(n), int(d), int(m), int(seed), ws.data_ptr(), ws.numel(),
+                                 _stream(ws)), "sng_sample")
+    return ws
 
 
 def cluster(X: torch.Tensor, m: int, eps: float, seed: int, min_pts: int, deg: torch.Tensor,

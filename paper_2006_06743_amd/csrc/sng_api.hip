@@ -156,6 +156,10 @@ int check_cfg(const sng_config *cfg)
         return SNG_EINVAL;
     if (cfg->schedule < 0 || cfg->schedule > 2)
         return SNG_EINVAL;
+    if (cfg->reuse_sample != 0 && cfg->reuse_sample != 1)
+        return SNG_EINVAL;
+    if (cfg->reuse_sample && (cfg->schedule == 1 || cfg->stage_lds))
+        return SNG_EINVAL;  // a stored sample is evaluated by the partner-block schedule only
     return SNG_OK;
 }
 
@@ -184,17 +188,20 @@ int pick_bucket(const Inst &I, const sng_config *cfg, void *workspace, size_t ws
     if (I.m == 0 || I.n == 0)
         return SNG_OK;  // no sampled-distance pass to schedule
     const int sched = cfg ? cfg->schedule : 0;
+    const bool forced = sched == 2 || (cfg && cfg->reuse_sample);
     if (sched == 1 || (cfg && cfg->stage_lds))
-        return sched == 2 ? SNG_EINVAL : SNG_OK;
-    if (!bucket_geometry(I.n, I.d, I.m, sched == 2, B))
-        return sched == 2 ? SNG_ENOTIMPL : SNG_OK;
+        return forced ? SNG_EINVAL : SNG_OK;
+    if (!bucket_geometry(I.n, I.d, I.m, forced, B))
+        return forced ? SNG_ENOTIMPL : SNG_OK;
     if (align_up(used + bucket_bytes(*B)) > ws_bytes)
-        return sched == 2 ? SNG_EWORKSPACE : SNG_OK;
+        return forced ? SNG_EWORKSPACE : SNG_OK;
     Carve cv((char *)workspace + used);
     B->rec = cv.take<uint32_t>(B->ranges * B->region);
     B->seg = cv.take<uint32_t>(B->ranges * B->NJ * 2);
     B->start = cv.take<uint32_t>(B->ranges * 2);
     B->queue = cv.take<unsigned long long>(kXcds);
+    B->hdr = I.cnt + kSampleHdr;
+    B->tag = sample_tag(I.n, I.m, (uint64_t)I.key0 | ((uint64_t)I.key1 << 32), B->bshift);
     *use = true;
     return SNG_OK;
 }
@@ -212,7 +219,8 @@ int run_plain(Inst &I, const sng_config *cfg, bool labels_wanted, const BucketGe
     SNG_TRY(launch_fill_u32(I.deg, I.n, 0u, st));
     if (I.m > 0 && B) {
         SNG_TRY(launch_fill_u32(I.mask, I.chunks * 8, 0u, st));
-        SNG_TRY(launch_bucket_plain(I, *B, shape_for(I, cfg, true), st));
+        SNG_TRY(launch_bucket_plain(I, *B, shape_for(I, cfg, true),
+                                    cfg && cfg->reuse_sample, st));
     } else if (I.m > 0) {
         SNG_TRY(launch_pass_a(I, shape_for(I, cfg), st));
     }
@@ -300,6 +308,37 @@ int sng_degrees(const float *X, int64_t n, int32_t d, int64_t ld, int64_t m, dou
     return run_plain(I, cfg, false, use ? &B : nullptr, st);
 }
 
+int sng_sample(int64_t n, int32_t d, int64_t m, uint64_t seed, void *workspace, size_t ws_bytes,
+               void *stream)
+{
+    if (n < 0 || d < 1 || m < 0)
+        return SNG_EINVAL;
+    if (n > kMaxN || m > kMaxM)
+        return SNG_ERANGE;
+    const size_t need = plain_ws_bytes(n, m);
+    if (!workspace || ws_bytes < need)
+        return SNG_EWORKSPACE;
+    hipStream_t st = (hipStream_t)stream;
+    Carve cv(workspace);
+    Inst I = make_inst(nullptr, n, d, d, m, 0.0, seed, 0);
+    I.cnt = cv.take<unsigned long long>(kHeaderBytes / 8);
+    (void)cv.take<uint32_t>((size_t)n);
+    (void)cv.take<uint8_t>((size_t)n);
+    (void)cv.take<uint32_t>(sizes_for(n, m).chunks * 8);
+    if (n == 0 || m == 0)
+        return SNG_OK;  // an empty sample: sng_degrees has nothing to evaluate
+    sng_config force;
+    memset(&force, 0, sizeof(force));
+    force.schedule = 2;
+    BucketGeom B;
+    bool use = false;
+    int rc = pick_bucket(I, &force, workspace, ws_bytes, cv.off, &B, &use);
+    if (rc)
+        return rc;
+    SNG_TRY(launch_bucket_generate(I, B, st));
+    return SNG_OK;
+}
+
 int sng_cluster(const float *X, int64_t n, int32_t d, int64_t ld, int64_t m, double eps,
                 uint64_t seed, int32_t min_pts, const uint32_t *degrees, int32_t *labels,
                 void *workspace, size_t ws_bytes, void *stream)
@@ -363,7 +402,8 @@ int sng_dbscan_lowp(const float *X, int64_t n, int32_t d, int64_t ld, const uint
                     int32_t min_pts, uint64_t seed, int32_t *labels, uint32_t *degrees,
                     void *workspace, size_t ws_bytes, const sng_config *cfg, void *stream)
 {
-    (void)cfg;
+    if (cfg && cfg->reuse_sample)
+        return SNG_EINVAL;  // the mixed form draws its own sample
     int rc = check_points(X, n, d, ld);
     if (rc) return rc;
     if ((rc = check_eps(eps))) return rc;
@@ -517,6 +557,7 @@ int sng_dbscan_sweep(const float *X, int64_t n, int32_t d, int64_t ld, double s,
     int rc = check_points(X, n, d, ld);
     if (rc) return rc;
     if ((rc = check_cfg(cfg))) return rc;
+    if (cfg && cfg->reuse_sample) return SNG_EINVAL;  // its workspace layout differs
     if (!eps || !min_pts || n_eps < 1 || n_minpts < 1) return SNG_EINVAL;
     if (n_eps > kSweepMaxK || n_minpts > kSweepMaxP) return SNG_ERANGE;
     for (int k = 0; k < n_eps; ++k) {

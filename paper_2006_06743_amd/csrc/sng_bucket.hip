@@ -218,9 +218,42 @@ __global__ __launch_bounds__(kGenThreads) void k_bkt_generate(Inst I, BucketGeom
                 dst[e] = stage[e];
         }
     }
-    const int slots[1] = {kCntSelf};
+    const int slots[1] = {1};
     const uint32_t sv[1] = {self};
-    block_count_add<1>(I.cnt, slots, sv);
+    block_count_add<1>(B.hdr, slots, sv);
+}
+
+// Before generate: no valid sample, no self pairs counted yet.
+__global__ void k_bkt_prepare(BucketGeom B, int clear_sample)
+{
+    const int t = threadIdx.x;
+    if (t < kXcds)
+        B.queue[t] = 0ull;
+    if (clear_sample && t < 2)
+        B.hdr[t] = 0ull;
+}
+
+// After generate: the records now hold the sample of B.tag.
+__global__ void k_bkt_seal(BucketGeom B)
+{
+    if (threadIdx.x == 0)
+        B.hdr[0] = B.tag;
+}
+
+// Every evaluate kernel starts here: false (and one count in the overflow
+// counter) when the workspace does not hold the sample of B.tag, so a stale
+// or missing sample is reported instead of read. Uniform over the grid.
+__device__ __forceinline__ bool sample_ok(const Inst &I, const BucketGeom &B)
+{
+    const unsigned long long have = B.hdr[0];
+    if (have != B.tag) {
+        if (blockIdx.x == 0 && threadIdx.x == 0)
+            atomicAdd(I.cnt + kCntOverflow, 1ull);
+        return false;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0)
+        atomicAdd(I.cnt + kCntSelf, B.hdr[1]);
+    return true;
 }
 
 // ---------------------------------------------------------------------------
@@ -400,6 +433,8 @@ __device__ __forceinline__ void eval_all(const Inst &I, const BucketGeom &B, Pol
 template <class Row, int OB>
 __global__ __launch_bounds__(256) void k_bkt_eval_plain(Inst I, BucketGeom B)
 {
+    if (!sample_ok(I, B))
+        return;
     BucketPlainPolicy pol;
     pol.deg = I.deg;
     pol.mask = I.mask;
@@ -414,6 +449,8 @@ __global__ __launch_bounds__(256) void k_bkt_eval_plain(Inst I, BucketGeom B)
 template <class Row, int OB>
 __global__ __launch_bounds__(256) void k_bkt_eval_sweep(Inst I, BucketGeom B, SweepArgs S)
 {
+    if (!sample_ok(I, B))
+        return;
     __shared__ float s_lo[kSweepMaxK], s_hi[kSweepMaxK];
     __shared__ double s_e2[kSweepMaxK];
     for (int k = threadIdx.x; k < S.K; k += blockDim.x) {
@@ -471,15 +508,41 @@ size_t bucket_bytes(const BucketGeom &g)
            (size_t)g.ranges * 8 + kXcds * 8 + 1280;
 }
 
-static hipError_t generate(const Inst &I, const BucketGeom &B, hipStream_t st)
+uint64_t sample_tag(int64_t n, int64_t m, uint64_t seed, uint32_t bshift)
 {
-    hipError_t e0 = launch_fill_u64(B.queue, kXcds, 0ull, st);
-    if (e0 != hipSuccess)
-        return e0;
+    // splitmix64 finaliser over the arguments that fix the records
+    uint64_t h = 0x9E3779B97F4A7C15ull;
+    const uint64_t parts[4] = {(uint64_t)n, (uint64_t)m, seed, (uint64_t)bshift};
+    for (uint64_t v : parts) {
+        h ^= v + 0x9E3779B97F4A7C15ull + (h << 6) + (h >> 2);
+        h ^= h >> 30;
+        h *= 0xBF58476D1CE4E5B9ull;
+        h ^= h >> 27;
+        h *= 0x94D049BB133111EBull;
+        h ^= h >> 31;
+    }
+    return h | 1ull;
+}
+
+hipError_t launch_bucket_generate(const Inst &I, const BucketGeom &B, hipStream_t st)
+{
     if (B.ranges > 0x7FFFFFFFull || B.NJ > kMaxPartnerBlocks)
         return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_bkt_prepare, dim3(1), dim3(64), 0, st, B, 1);
     hipLaunchKernelGGL(k_bkt_generate, dim3((unsigned)B.ranges), dim3(kGenThreads),
                        ((size_t)kRangeSlots + 2 * (size_t)B.NJ) * sizeof(uint32_t), st, I, B);
+    hipLaunchKernelGGL(k_bkt_seal, dim3(1), dim3(64), 0, st, B);
+    return hipGetLastError();
+}
+
+static hipError_t prepare_eval(const Inst &I, const BucketGeom &B, bool reuse, hipStream_t st)
+{
+    if (!reuse) {
+        const hipError_t e = launch_bucket_generate(I, B, st);
+        if (e != hipSuccess)
+            return e;
+    }
+    hipLaunchKernelGGL(k_bkt_prepare, dim3(1), dim3(64), 0, st, B, 0);
     return hipGetLastError();
 }
 
@@ -491,9 +554,9 @@ static unsigned eval_blocks(const BucketGeom &B)
 }
 
 hipError_t launch_bucket_plain(const Inst &I, const BucketGeom &B, const PassAShape &sh,
-                               hipStream_t st)
+                               bool reuse, hipStream_t st)
 {
-    hipError_t e = generate(I, B, st);
+    hipError_t e = prepare_eval(I, B, reuse, st);
     if (e != hipSuccess)
         return e;
     const bool vec_ok = ((uintptr_t)I.X % 16 == 0) && (I.ld % 4 == 0);
@@ -511,7 +574,7 @@ hipError_t launch_bucket_plain(const Inst &I, const BucketGeom &B, const PassASh
 hipError_t launch_bucket_sweep(const Inst &I, const SweepArgs &S, const BucketGeom &B,
                                const PassAShape &sh, hipStream_t st)
 {
-    hipError_t e = generate(I, B, st);
+    hipError_t e = prepare_eval(I, B, false, st);
     if (e != hipSuccess)
         return e;
     const bool vec_ok = ((uintptr_t)I.X % 16 == 0) && (I.ld % 4 == 0);

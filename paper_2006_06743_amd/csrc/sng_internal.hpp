@@ -87,12 +87,20 @@ struct BucketGeom {
     uint32_t *rec;       // [ranges][region] 4-byte slot records
     uint32_t *seg;       // [ranges][NJ][2] segment offset and count
     uint32_t *start;     // [ranges][2] source and call of each range's first call
-    unsigned long long *queue;  // [kXcds] next segment of each XCD's queue
+    unsigned long long *queue;  // [kXcds] next ticket of each XCD's queue
+    unsigned long long *hdr;    // [2] tag of the sample held in rec, and its self-pair count
+    uint64_t tag;               // tag of the sample these arguments describe (never 0)
 };
+// u64 index of BucketGeom::hdr inside an instance's counter header
+constexpr int kSampleHdr = 32;
+uint64_t sample_tag(int64_t n, int64_t m, uint64_t seed, uint32_t bshift);
 bool bucket_geometry(int64_t n, int d, int64_t m, bool force, BucketGeom *g);
 size_t bucket_bytes(const BucketGeom &g);
+// Draws and sorts the sample into B (B.hdr gets its tag once complete).
+hipError_t launch_bucket_generate(const Inst &I, const BucketGeom &B, hipStream_t st);
+// Evaluates the sample held in B, drawing it first unless `reuse`.
 hipError_t launch_bucket_plain(const Inst &I, const BucketGeom &B, const PassAShape &sh,
-                               hipStream_t st);
+                               bool reuse, hipStream_t st);
 hipError_t launch_bucket_sweep(const Inst &I, const SweepArgs &S, const BucketGeom &B,
                                const PassAShape &sh, hipStream_t st);
 

@@ -248,3 +248,55 @@ def test_compact_labels(sng, orc, n):
         assert k == kr
         bad = np.nonzero(got != ref)[0]
         assert bad.size == 0, "%d ids differ (first %s)" % (bad.size, bad[:5])
+
+
+def test_sample_reused_across_eps_and_inputs(sng, orc):
+    """sng_sample once, then sng_degrees / sng_dbscan with reuse_sample at
+    several eps values and on a second X of the same shape: every result
+    equals the oracle's single run."""
+    import torch
+    rng = np.random.default_rng(515)
+    n, d, s = 20000, 5, 0.01
+    m = orc.samples_per_point(s, n)
+    seed = int(rng.integers(0, 2**63))
+    X1 = wl.random_instance(rng, n, d, "blobs", spread=0.03)
+    X2 = wl.random_instance(rng, n, d, "blobs", spread=0.05)
+    ws = torch.zeros(sng.workspace_size(n, d, m), dtype=torch.uint8, device="cuda")
+    sng.sample(n, d, m, seed, ws)
+    reuse = sng.Config(reuse_sample=1)
+    for X in (X1, X2):
+        Xg = to_gpu(X)
+        for eps, mp in [(0.02, 3), (0.05, 4), (0.2, 6)]:
+            print("reuse eps", eps, flush=True)
+            deg, _ = sng.degrees(Xg, m, eps, seed, cfg=reuse, ws=ws)
+            lab, deg2, _ = sng.dbscan(Xg, s, eps, mp, seed, cfg=reuse, ws=ws)
+            torch.cuda.synchronize()
+            st = sng.stats(ws)
+            ref = orc.dbscan(X, eps, mp, seed, s=s)
+            assert st.overflow == 0 and st.self_pairs == ref.self_pairs
+            assert_same(lab.cpu().numpy(), deg2.cpu().numpy().view(np.uint32), ref, "dbscan")
+            assert np.array_equal(deg.cpu().numpy().view(np.uint32), ref.deg)
+
+
+def test_stale_sample_is_reported(sng, orc):
+    """A reuse call whose sample is missing (fresh workspace) or was drawn
+    with another seed does no work and is reported through the overflow
+    counter."""
+    import torch
+    rng = np.random.default_rng(516)
+    n, d, m = 5000, 3, 40
+    Xg = to_gpu(wl.random_instance(rng, n, d, "blobs"))
+    reuse = sng.Config(reuse_sample=1)
+    ws = torch.zeros(sng.workspace_size(n, d, m), dtype=torch.uint8, device="cuda")
+    deg, _ = sng.degrees(Xg, m, 0.05, 7, cfg=reuse, ws=ws)
+    torch.cuda.synchronize()
+    assert sng.stats(ws).overflow >= 1
+    assert int(deg.abs().sum()) == 0
+    sng.sample(n, d, m, 8, ws)
+    deg, _ = sng.degrees(Xg, m, 0.05, 7, cfg=reuse, ws=ws)
+    torch.cuda.synchronize()
+    assert sng.stats(ws).overflow >= 1
+    deg, _ = sng.degrees(Xg, m, 0.05, 8, cfg=reuse, ws=ws)
+    torch.cuda.synchronize()
+    st = sng.stats(ws)
+    assert st.overflow == 0 and st.accepted > 0
