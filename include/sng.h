@@ -147,6 +147,32 @@ int sng_degrees(const float *X, int64_t n, int32_t d, int64_t ld, int64_t m, dou
 int sng_sample(int64_t n, int32_t d, int64_t m, uint64_t seed, void *workspace, size_t ws_bytes,
                void *stream);
 
+/* Autotuner of the sampled-distance pass. Runs sng_degrees on the caller's
+ * data once per candidate configuration (lanes per pair around the default,
+ * 4/8/16 rows in flight, 8 or 16 chunks per wave, LDS staging for wide rows,
+ * direct gathers and, where it applies and the workspace holds its records,
+ * the partner-block schedule), `trials` timed runs each after one warm-up,
+ * timed with HIP events on `stream`, and writes the fastest to *best (host)
+ * and its mean time in ms to *best_ms (host, may be NULL); *tried (host, may
+ * be NULL) gets the number of candidates timed. Every candidate computes
+ * the same degrees. The result is also stored in a process-wide cache
+ * (mutex-protected) under the key (d, 16-byte row alignment, ceil(log2 n),
+ * ceil(log2 m)); sng_degrees, sng_dbscan and sng_dbscan_sweep calls with
+ * cfg == NULL or an all-zero config of that key then run with it (a tuned
+ * partner-block schedule falls back to direct gathers when the workspace
+ * lacks room). Synchronises the stream. Workspace as for sng_degrees; the
+ * degrees it computes stay inside it. n = 0 or m = 0: nothing to tune,
+ * *best is all zero. */
+int sng_autotune(const float *X, int64_t n, int32_t d, int64_t ld, int64_t m, double eps,
+                 uint64_t seed, void *workspace, size_t ws_bytes, int32_t trials,
+                 sng_config *best, float *best_ms, int32_t *tried, void *stream);
+/* The cached configuration for this shape class (X only for its alignment),
+ * or SNG_ENOTIMPL when none is cached. Host call. */
+int sng_autotune_lookup(const float *X, int64_t n, int32_t d, int64_t ld, int64_t m,
+                        sng_config *out);
+/* Empties the autotune cache. Host call. */
+int sng_autotune_clear(void);
+
 /* Post-processing (Algorithm 1: core points, components of the core
  * subgraph, border assignment) continuing from the accept bits that the last
  * sng_degrees call left in the same workspace (same X, n, d, ld, m, eps and

@@ -18,6 +18,7 @@ from . import _lib
 from ._lib import SNG_BF16, SNG_FP16, SNG_FP32, SNGError, check, sng_config, sng_stats
 
 __all__ = ["dbscan", "dbscan_lowp", "degrees", "sample", "cluster", "compact_labels",
+           "autotune", "autotune_lookup", "autotune_clear",
            "graph_labels", "sweep", "batch", "BatchPlan",
            "samples_per_point", "Config", "Stats", "SNGError", "SNG_FP32", "SNG_BF16",
            "SNG_FP16", "load"]
@@ -124,6 +125,45 @@ def sample(n: int, d: int, m: int, seed: int, ws: torch.Tensor):
     check(_lib.load().sng_sample(int(n), int(d), int(m), int(seed), ws.data_ptr(), ws.numel(),
                                  _stream(ws)), "sng_sample")
     return ws
+
+
+def _config_of(c) -> Config:
+    return Config(c.lanes_per_pair, c.chunks_per_wave, c.stage_lds, c.prefetch, c.schedule,
+                  c.reuse_sample)
+
+
+def autotune(X: torch.Tensor, m: int, eps: float, seed: int, trials: int = 2,
+             ws: Optional[torch.Tensor] = None):
+    """Times the launch shapes and schedules of the sampled-distance pass on X
+    and caches the fastest for calls without a config. Returns
+    (Config, mean ms, candidates timed)."""
+    n, d, ld = _rows(X)
+    if ws is None:
+        ws = _ws(workspace_size(n, d, m), X.device)
+    best = sng_config()
+    ms = ctypes.c_float()
+    tried = ctypes.c_int32()
+    check(_lib.load().sng_autotune(X.data_ptr() if n else None, n, d, ld, int(m), float(eps),
+                                   int(seed), ws.data_ptr(), ws.numel(), int(trials),
+                                   ctypes.byref(best), ctypes.byref(ms), ctypes.byref(tried),
+                                   _stream(X)), "sng_autotune")
+    return _config_of(best), ms.value, tried.value
+
+
+def autotune_lookup(X: torch.Tensor, m: int) -> Optional[Config]:
+    """The cached tuned config for X's shape class, or None."""
+    n, d, ld = _rows(X)
+    out = sng_config()
+    rc = _lib.load().sng_autotune_lookup(X.data_ptr() if n else None, n, d, ld, int(m),
+                                         ctypes.byref(out))
+    if rc == _lib.SNG_ENOTIMPL:
+        return None
+    check(rc, "sng_autotune_lookup")
+    return _config_of(out)
+
+
+def autotune_clear():
+    check(_lib.load().sng_autotune_clear(), "sng_autotune_clear")
 
 
 def cluster(X: torch.Tensor, m: int, eps: float, seed: int, min_pts: int, deg: torch.Tensor,

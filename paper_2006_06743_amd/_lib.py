@@ -19,7 +19,8 @@ SNG_FP32, SNG_BF16, SNG_FP16 = 0, 1, 2
 EXPORTS = [
     "sng_status_string", "sng_samples_per_point", "sng_workspace_size", "sng_degrees",
     "sng_cluster", "sng_dbscan", "sng_dbscan_lowp", "sng_graph_workspace_size", "sng_graph_labels",
-    "sng_compact_labels", "sng_sample",
+    "sng_compact_labels", "sng_sample", "sng_autotune", "sng_autotune_lookup",
+    "sng_autotune_clear",
     "sng_sweep_workspace_size", "sng_dbscan_sweep", "sng_batch_workspace_size",
     "sng_dbscan_batch", "sng_batch_plan_create", "sng_batch_plan_launch",
     "sng_batch_plan_destroy", "sng_stats_read",
@@ -75,6 +76,10 @@ def load() -> ctypes.CDLL:
         "sng_graph_labels": ([i64, P, i64, i32, P, P, P, sz, P], ctypes.c_int),
         "sng_compact_labels": ([P, i64, P, P, P], ctypes.c_int),
         "sng_sample": ([i64, i32, i64, u64, P, sz, P], ctypes.c_int),
+        "sng_autotune": ([P, i64, i32, i64, i64, dbl, u64, P, sz, i32, cfgp, P, P, P],
+                         ctypes.c_int),
+        "sng_autotune_lookup": ([P, i64, i32, i64, i64, cfgp], ctypes.c_int),
+        "sng_autotune_clear": ([], ctypes.c_int),
         "sng_sweep_workspace_size": ([i64, i32, i64, i32, i32, ctypes.POINTER(sz)],
                                      ctypes.c_int),
         "sng_dbscan_sweep": ([P, i64, i32, i64, dbl, P, i32, P, i32, u64, P, P, P, sz, cfgp, P],

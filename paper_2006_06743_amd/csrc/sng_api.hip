@@ -3,6 +3,9 @@
 #include <math.h>
 #include <string.h>
 
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <vector>
 
 #include "../../include/sng.h"
@@ -178,6 +181,61 @@ hipError_t init_header(unsigned long long *cnt, uint64_t slots, double band, hip
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Autotune cache: the fastest configuration found by sng_autotune for a
+// shape class, used by calls that pass no configuration of their own.
+// ---------------------------------------------------------------------------
+constexpr int kPreferPartner = 3;  // internal schedule: partner blocks when they fit, else direct
+
+struct TuneKey {
+    int d, vec, lg_n, lg_m;
+    bool operator<(const TuneKey &o) const
+    {
+        return std::tie(d, vec, lg_n, lg_m) < std::tie(o.d, o.vec, o.lg_n, o.lg_m);
+    }
+};
+
+std::mutex g_tune_mu;
+std::map<TuneKey, sng_config> g_tune;
+
+int ceil_log2(uint64_t v)
+{
+    int r = 0;
+    while (r < 63 && ((uint64_t)1 << r) < v)
+        ++r;
+    return r;
+}
+
+TuneKey tune_key(const float *X, int32_t d, int64_t ld, int64_t n, int64_t m)
+{
+    const int vec = ((uintptr_t)X % 16 == 0) && (ld % 4 == 0);
+    return TuneKey{d, vec, ceil_log2((uint64_t)n), ceil_log2((uint64_t)m)};
+}
+
+bool is_default_cfg(const sng_config *cfg)
+{
+    return !cfg || (cfg->lanes_per_pair == 0 && cfg->chunks_per_wave == 0 && cfg->stage_lds == 0 &&
+                    cfg->prefetch == 0 && cfg->schedule == 0 && cfg->reuse_sample == 0);
+}
+
+// The configuration a call runs with: the caller's own, or for a call without
+// one the tuned configuration of its shape class if there is one. A tuned
+// partner-block schedule becomes a preference, so a workspace sized for
+// direct gathers still works.
+const sng_config *effective_cfg(const Inst &I, const sng_config *cfg, sng_config *buf)
+{
+    if (!is_default_cfg(cfg))
+        return cfg;
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    const auto it = g_tune.find(tune_key(I.X, I.d, I.ld, I.n, I.m));
+    if (it == g_tune.end())
+        return cfg;
+    *buf = it->second;
+    if (buf->schedule == 2)
+        buf->schedule = kPreferPartner;
+    return buf;
+}
+
 // Chooses the schedule of the sampled-distance pass: the partner-block
 // schedule when it applies, the caller allows it and the workspace holds its
 // records (carved after `used` bytes); otherwise direct gathers.
@@ -191,7 +249,7 @@ int pick_bucket(const Inst &I, const sng_config *cfg, void *workspace, size_t ws
     const bool forced = sched == 2 || (cfg && cfg->reuse_sample);
     if (sched == 1 || (cfg && cfg->stage_lds))
         return forced ? SNG_EINVAL : SNG_OK;
-    if (!bucket_geometry(I.n, I.d, I.m, forced, B))
+    if (!bucket_geometry(I.n, I.d, I.m, forced || sched == kPreferPartner, B))
         return forced ? SNG_ENOTIMPL : SNG_OK;
     if (align_up(used + bucket_bytes(*B)) > ws_bytes)
         return forced ? SNG_EWORKSPACE : SNG_OK;
@@ -302,6 +360,8 @@ int sng_degrees(const float *X, int64_t n, int32_t d, int64_t ld, int64_t m, dou
     I.mask = cv.take<uint32_t>(sizes_for(n, m).chunks * 8);
     I.deg = degrees;
     I.labels = nullptr;
+    sng_config tuned;
+    cfg = effective_cfg(I, cfg, &tuned);
     BucketGeom B;
     bool use = false;
     if ((rc = pick_bucket(I, cfg, workspace, ws_bytes, cv.off, &B, &use))) return rc;
@@ -336,6 +396,131 @@ int sng_sample(int64_t n, int32_t d, int64_t m, uint64_t seed, void *workspace, 
     if (rc)
         return rc;
     SNG_TRY(launch_bucket_generate(I, B, st));
+    return SNG_OK;
+}
+
+int sng_autotune(const float *X, int64_t n, int32_t d, int64_t ld, int64_t m, double eps,
+                 uint64_t seed, void *workspace, size_t ws_bytes, int32_t trials,
+                 sng_config *best, float *best_ms, int32_t *tried, void *stream)
+{
+    int rc = check_points(X, n, d, ld);
+    if (rc) return rc;
+    if ((rc = check_eps(eps))) return rc;
+    if (m < 0 || !best || trials < 1 || trials > 1000) return SNG_EINVAL;
+    if (m > kMaxM) return SNG_ERANGE;
+    const size_t need = plain_ws_bytes(n, m);
+    if (!workspace || ws_bytes < need) return SNG_EWORKSPACE;
+    memset(best, 0, sizeof(*best));
+    if (best_ms) *best_ms = 0.0f;
+    if (tried) *tried = 0;
+    if (n == 0 || m == 0)
+        return SNG_OK;  // no sampled-distance pass to tune
+    hipStream_t st = (hipStream_t)stream;
+    Carve cv(workspace);
+    Inst I = make_inst(X, n, d, ld, m, eps, seed, 0);
+    I.cnt = cv.take<unsigned long long>(kHeaderBytes / 8);
+    I.deg = cv.take<uint32_t>((size_t)n);
+    I.core = cv.take<uint8_t>((size_t)n);
+    I.mask = cv.take<uint32_t>(sizes_for(n, m).chunks * 8);
+    I.labels = nullptr;
+
+    // Candidates: lanes per pair around the default, rows in flight, chunks
+    // per wave (direct), LDS staging for wide rows, and both schedules; the
+    // shapes that resolve to the same launch are tried once.
+    const bool vec_ok = ((uintptr_t)X % 16 == 0) && (ld % 4 == 0);
+    const int g0 = resolve_shape(d, vec_ok, 0, 0, 0, 0).lanes;
+    std::vector<sng_config> cand;
+    std::vector<std::tuple<int, int, int, int, int>> seen;
+    auto add = [&](int sched, int lanes, int cpw, int lds, int pf) {
+        const PassAShape s = resolve_shape(d, vec_ok, lanes, cpw, lds, pf);
+        const auto key = std::make_tuple(sched, s.lanes, sched == 2 ? 0 : s.chunks_per_wave,
+                                         s.stage_lds, s.owners_per_batch);
+        for (const auto &k : seen)
+            if (k == key) return;
+        seen.push_back(key);
+        sng_config c;
+        memset(&c, 0, sizeof(c));
+        c.schedule = sched;
+        c.lanes_per_pair = s.lanes;
+        c.chunks_per_wave = sched == 2 ? 0 : s.chunks_per_wave;
+        c.stage_lds = s.stage_lds;
+        c.prefetch = 4 * s.owners_per_batch;
+        cand.push_back(c);
+    };
+    for (int g : {g0, g0 / 2, g0 * 2}) {
+        if (g < 1 || g > 64) continue;
+        for (int pf : {4, 8, 16}) {
+            for (int cpw : {8, 16})
+                add(1, g, cpw, 0, pf);
+            add(2, g, 0, 0, pf);
+        }
+    }
+    if (d >= 256 && d <= 4096)
+        add(1, 64, 8, 1, 4);
+
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        return SNG_EHIP;
+    }
+    float best_t = -1.0f;
+    int n_tried = 0;
+    rc = SNG_OK;
+    for (const sng_config &c : cand) {
+        BucketGeom B;
+        bool use = false;
+        if (pick_bucket(I, &c, workspace, ws_bytes, cv.off, &B, &use) != SNG_OK)
+            continue;  // this schedule does not apply, or the workspace lacks its records
+        const BucketGeom *bp = use ? &B : nullptr;
+        if ((rc = run_plain(I, &c, false, bp, st)) != SNG_OK)  // warm-up
+            break;
+        if (hipEventRecord(e0, st) != hipSuccess) { rc = SNG_EHIP; break; }
+        for (int k = 0; k < trials && rc == SNG_OK; ++k)
+            rc = run_plain(I, &c, false, bp, st);
+        if (rc != SNG_OK) break;
+        float ms = 0.0f;
+        if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+            rc = SNG_EHIP;
+            break;
+        }
+        ms /= (float)trials;
+        ++n_tried;
+        if (best_t < 0.0f || ms < best_t) {
+            best_t = ms;
+            *best = c;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != SNG_OK)
+        return rc;
+    if (tried) *tried = n_tried;
+    if (best_t < 0.0f)
+        return SNG_ENOTIMPL;
+    if (best_ms) *best_ms = best_t;
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    g_tune[tune_key(X, d, ld, n, m)] = *best;
+    return SNG_OK;
+}
+
+int sng_autotune_lookup(const float *X, int64_t n, int32_t d, int64_t ld, int64_t m,
+                        sng_config *out)
+{
+    if (!out || n < 0 || d < 1 || ld < d || m < 0)
+        return SNG_EINVAL;
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    const auto it = g_tune.find(tune_key(X, d, ld, n, m));
+    if (it == g_tune.end())
+        return SNG_ENOTIMPL;
+    *out = it->second;
+    return SNG_OK;
+}
+
+int sng_autotune_clear(void)
+{
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    g_tune.clear();
     return SNG_OK;
 }
 
@@ -391,6 +576,8 @@ int sng_dbscan(const float *X, int64_t n, int32_t d, int64_t ld, double s, doubl
     I.mask = cv.take<uint32_t>(sizes_for(n, m).chunks * 8);
     I.deg = degrees ? degrees : wdeg;
     I.labels = labels;
+    sng_config tuned;
+    cfg = effective_cfg(I, cfg, &tuned);
     BucketGeom B;
     bool use = false;
     if ((rc = pick_bucket(I, cfg, workspace, ws_bytes, cv.off, &B, &use))) return rc;
@@ -596,6 +783,8 @@ int sng_dbscan_sweep(const float *X, int64_t n, int32_t d, int64_t ld, double s,
     }
     BucketGeom B;
     bool use = false;
+    sng_config tuned;
+    cfg = effective_cfg(I, cfg, &tuned);
     if ((rc = pick_bucket(I, cfg, workspace, ws_bytes, cv.off, &B, &use))) return rc;
     SNG_TRY(init_header(I.cnt, (uint64_t)n * (uint64_t)m, band, st));
     SNG_TRY(launch_fill_u32(S.hist, (uint64_t)n * n_eps, 0u, st));

@@ -114,3 +114,28 @@ def test_invalid_arguments_rejected_before_launch(lib):
         c = sng_config(*fields)
         assert lib.sng_dbscan(fake, 10, 2, 2, 0.5, 1.0, 3, 1, lab, None, ws, 10**9,
                               ctypes.byref(c), None) == -1, fields
+
+
+def test_autotune_arguments_and_cache(lib):
+    from paper_2006_06743_amd._lib import sng_config
+    fake = ctypes.c_void_p(0x1000)
+    ws = ctypes.c_void_p(0x2000)
+    best = sng_config()
+    ms = ctypes.c_float()
+    # validation before any launch
+    assert lib.sng_autotune(fake, 10, 2, 2, 5, 0.1, 1, ws, 10**9, 0, ctypes.byref(best),
+                            None, None, None) == -1          # trials < 1
+    assert lib.sng_autotune(fake, 10, 2, 2, 5, 0.1, 1, ws, 10**9, 2, None, None, None,
+                            None) == -1                      # no output
+    assert lib.sng_autotune(fake, 10, 2, 2, 5, -1.0, 1, ws, 10**9, 2, ctypes.byref(best),
+                            None, None, None) == -1          # eps < 0
+    assert lib.sng_autotune(fake, 10, 2, 2, 5, 0.1, 1, ws, 10, 2, ctypes.byref(best),
+                            None, None, None) == -3          # workspace too small
+    # nothing to tune: m = 0 returns an all-zero config without touching the device
+    assert lib.sng_autotune(fake, 10, 2, 2, 0, 0.1, 1, ws, 10**9, 2, ctypes.byref(best),
+                            ctypes.byref(ms), None, None) == 0
+    assert best.schedule == 0 and best.lanes_per_pair == 0 and ms.value == 0.0
+    assert lib.sng_autotune_clear() == 0
+    out = sng_config()
+    assert lib.sng_autotune_lookup(fake, 10, 2, 2, 5, ctypes.byref(out)) == -6
+    assert lib.sng_autotune_lookup(fake, 10, 2, 2, 5, None) == -1

@@ -300,3 +300,34 @@ def test_stale_sample_is_reported(sng, orc):
     torch.cuda.synchronize()
     st = sng.stats(ws)
     assert st.overflow == 0 and st.accepted > 0
+
+
+@pytest.mark.parametrize("n,d,s", [(40000, 16, 0.002), (60000, 3, 0.002)])
+def test_autotune_and_tuned_calls(sng, orc, n, d, s):
+    """The autotuner times its candidates, caches the fastest, and calls
+    without a config then run with it; results stay the oracle's."""
+    import torch
+    rng = np.random.default_rng(808 + d)
+    X = wl.random_instance(rng, n, d, "blobs", spread=0.03)
+    seed = int(rng.integers(0, 2**63))
+    m = orc.samples_per_point(s, n)
+    Xg = to_gpu(X)
+    sng.autotune_clear()
+    assert sng.autotune_lookup(Xg, m) is None
+    print("autotune", n, d, flush=True)
+    best, ms, tried = sng.autotune(Xg, m, 0.02, seed, trials=1)
+    assert tried >= 3 and ms > 0.0
+    assert best.schedule in (1, 2) and best.lanes_per_pair >= 1 and best.prefetch in (4, 8, 16)
+    assert sng.autotune_lookup(Xg, m) == best
+    gl, gd, st = run(sng, X, s, 0.02, 3, seed)  # no config: the tuned one
+    ref = orc.dbscan(X, 0.02, 3, seed, s=s)
+    assert_same(gl, gd, ref, "tuned n=%d d=%d" % (n, d))
+    # a workspace sized for direct gathers only still works with a tuned
+    # partner-block preference
+    ws = torch.zeros(sng.workspace_size(n, d, m, sng.SNG_FP32 | 0x100), dtype=torch.uint8,
+                     device="cuda")
+    lab, deg, _ = sng.dbscan(Xg, s, 0.02, 3, seed, ws=ws)
+    torch.cuda.synchronize()
+    assert_same(lab.cpu().numpy(), deg.cpu().numpy().view(np.uint32), ref, "direct-sized ws")
+    sng.autotune_clear()
+    assert sng.autotune_lookup(Xg, m) is None
