@@ -237,30 +237,85 @@ __global__ __launch_bounds__(256) void k_lowp_pass_a(Inst I, LowpArgs L, int KS)
     block_count_add<2>(I.cnt, slots, v);
 }
 
-// Re-decides every queued slot with the defining binary64 sum.
-__global__ __launch_bounds__(256) void k_lowp_recheck(Inst I, LowpArgs L)
+// Re-decides every queued slot with the defining binary64 sum. A wavefront
+// takes 64 queued slots at a time, lane l owning slot l's sum. The squared
+// binary64 differences are independent of each other, so they are computed
+// kRecheckK coordinates at a time with coalesced row loads (two pairs per
+// step, one per half-wave) and parked in LDS; then each lane adds its own
+// pair's terms in coordinate order, which keeps the defining sequence of
+// roundings.
+constexpr int kRecheckK = 32;               // coordinates per LDS chunk
+constexpr int kRecheckStride = kWave + 1;   // doubles per LDS row (padding)
+constexpr int kRecheckWaves = 4;
+
+__global__ __launch_bounds__(kWave * kRecheckWaves) void k_lowp_recheck(Inst I, LowpArgs L)
 {
+#pragma clang fp contract(off)
+    __shared__ double terms[kRecheckWaves][kRecheckK * kRecheckStride];
+    double *T = terms[threadIdx.x / kWave];
+    const int lane = lane_id();
+    const int half = lane >> 5;
+    const int kl = lane & 31;
     const unsigned long long q = min((unsigned long long)I.cnt[kCntQueue],
                                      (unsigned long long)L.qcap);
-    uint32_t acc = 0;
-    for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < q;
-         e += (uint64_t)gridDim.x * blockDim.x) {
-        const uint64_t u = L.queue[e];
-        const uint64_t i = u / I.m;
-        const uint32_t t = (uint32_t)(u - i * I.m);
-        const Words4 W = philox10(t >> 2, (uint32_t)i, I.key0, I.key1);
-        const uint32_t j = mod_exact(W.w[t & 3], I.n, I.inv_n);
-        const double D = sqdist_f64(I.X + i * I.ld, I.X + (uint64_t)j * I.ld, I.d);
-        if (D <= I.eps2) {
+    const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const uint64_t waves = (uint64_t)gridDim.x * blockDim.x / kWave;
+    const int d = I.d;
+    uint32_t acc_n = 0;
+    for (uint64_t e0 = wave * kWave; e0 < q; e0 += waves * kWave) {  // wave-uniform
+        const uint64_t e = e0 + (uint64_t)lane;
+        const bool live = e < q;
+        uint32_t i = 0, j = 0, t = 0;
+        if (live) {
+            const uint64_t u = L.queue[e];
+            const uint64_t ii = u / I.m;
+            t = (uint32_t)(u - ii * I.m);
+            i = (uint32_t)ii;
+            const Words4 W = philox10(t >> 2, i, I.key0, I.key1);
+            j = mod_exact(W.w[t & 3], I.n, I.inv_n);
+        }
+        const int npairs = (int)min((uint64_t)kWave, q - e0);
+        double acc = 0.0;
+        for (int k0 = 0; k0 < d; k0 += kRecheckK) {
+            const int k = k0 + kl;
+            for (int pp = 0; pp < npairs; pp += 2) {  // wave-uniform
+                const uint32_t i0 = (uint32_t)__builtin_amdgcn_readlane((int)i, pp);
+                const uint32_t j0 = (uint32_t)__builtin_amdgcn_readlane((int)j, pp);
+                const int p1 = pp + 1 < npairs ? pp + 1 : pp;
+                const uint32_t i1 = (uint32_t)__builtin_amdgcn_readlane((int)i, p1);
+                const uint32_t j1 = (uint32_t)__builtin_amdgcn_readlane((int)j, p1);
+                const uint32_t ip = half ? i1 : i0;
+                const uint32_t jp = half ? j1 : j0;
+                double sq = 0.0;
+                if (k < d) {
+                    const double delta = (double)I.X[(uint64_t)ip * I.ld + k] -
+                                         (double)I.X[(uint64_t)jp * I.ld + k];
+                    sq = delta * delta;
+                }
+                T[kl * kRecheckStride + pp + half] = sq;
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            const int kn = min(kRecheckK, d - k0);
+            if (live) {
+                for (int c = 0; c < kn; ++c)
+                    acc = acc + T[c * kRecheckStride + lane];
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+        if (live && acc <= I.eps2) {
             atomicAdd(I.deg + i, 1u);
             atomicAdd(I.deg + j, 1u);
-            const uint64_t g = i * (uint64_t)I.C + (t >> 2);
+            const uint64_t g = (uint64_t)i * (uint64_t)I.C + (t >> 2);
             atomicOr(I.mask + (g >> 3), 1u << (4 * (g & 7) + (t & 3)));
-            acc += 1;
+            acc_n += 1;
         }
     }
     const int slots[1] = {kCntAccepted};
-    const uint32_t v[1] = {acc};
+    const uint32_t v[1] = {acc_n};
     block_count_add<1>(I.cnt, slots, v);
 }
 
@@ -299,7 +354,7 @@ hipError_t launch_lowp(const Inst &I, const LowpArgs &L, int prec, hipStream_t s
         hipLaunchKernelGGL(k_lowp_pass_a<2>, dim3(blocks), dim3(64 * waves), lds, st, I, L, KS);
     if ((e = hipGetLastError()) != hipSuccess)
         return e;
-    hipLaunchKernelGGL(k_lowp_recheck, dim3(2048), dim3(256), 0, st, I, L);
+    hipLaunchKernelGGL(k_lowp_recheck, dim3(1024), dim3(kWave * kRecheckWaves), 0, st, I, L);
     if ((e = hipGetLastError()) != hipSuccess)
         return e;
     hipLaunchKernelGGL(k_lowp_count_rechecked, dim3(1), dim3(64), 0, st, I.cnt);
