@@ -10,7 +10,8 @@ kernel, the oracle's CPU rate on a bounded sample, and the plain-vs-mixed,
 plain-vs-sweep and sequential-vs-batched comparisons.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--schedule auto|direct]
-                    [--no-forms] [--no-cpu-baseline] [--calibrate-copy]
+                    [--forms mixed,sweep,batch | --no-forms] [--no-cpu-baseline]
+                    [--calibrate-copy]
 """
 import argparse
 import dataclasses
@@ -107,99 +108,103 @@ def cpu_baseline(W, m, budget_s=15.0):
                       "in %.1f s" % (k - 1, slots, dt)}
 
 
-def time_forms(sng, torch, wl, reps=3):
-    """Plain vs mixed precision (784-d), plain vs one sweep (32-d grid),
-    sequential vs batched instances (64 uneven 3-d instances)."""
-    out = {}
-
-    def cuda_ms(fn, r=reps):
+def _cuda_ms(torch, fn, reps):
+    fn()
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
         fn()
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def form_mixed(sng, torch, wl, reps):
+    """Plain binary32 vs the bfloat16 MFMA form on the 784-d quantised images."""
+    W = wl.mnistlike_784d()
+    X = torch.from_numpy(W.X).cuda()
+    Xlp = torch.from_numpy(W.X_lp.view(__import__("numpy").int16)).cuda()
+    m = sng.samples_per_point(W.s, W.n)
+    lab, deg, ws = sng.dbscan(X, W.s, W.eps, W.min_pts, W.seed)
+    t_plain = _cuda_ms(torch, lambda: sng.dbscan(X, W.s, W.eps, W.min_pts, W.seed, labels=lab,
+                                                 degrees_out=deg, ws=ws), reps)
+    entry = {"workload": W.name, "slots": W.n * m, "plain_ms": t_plain}
+    try:
+        lab2, deg2, ws2 = sng.dbscan_lowp(X, Xlp, W.s, W.eps, W.min_pts, W.seed)
+        t_mixed = _cuda_ms(torch, lambda: sng.dbscan_lowp(X, Xlp, W.s, W.eps, W.min_pts,
+                                                          W.seed, ws=ws2), reps)
+        lab2, deg2, ws2 = sng.dbscan_lowp(X, Xlp, W.s, W.eps, W.min_pts, W.seed, ws=ws2)
         torch.cuda.synchronize()
-        a = torch.cuda.Event(enable_timing=True)
-        b = torch.cuda.Event(enable_timing=True)
-        a.record()
-        for _ in range(r):
-            fn()
-        b.record()
-        torch.cuda.synchronize()
-        return a.elapsed_time(b) / r
+        st = sng.stats(ws2)
+        entry.update({"mixed_bf16_ms": t_mixed, "speedup": t_plain / t_mixed,
+                      "labels_identical": bool(torch.equal(lab, lab2)),
+                      "degrees_identical": bool(torch.equal(deg, deg2)),
+                      "recheck_fraction": st.rechecked / max(1, st.slots),
+                      "band_rel": st.band_rel})
+    except sng.SNGError as e:
+        entry["mixed_bf16"] = "unavailable: %s" % e
+    return entry
 
-    # mixed precision on the 784-d quantised images
+
+def form_sweep(sng, torch, wl, reps):
+    """One sweep pass vs one plain call per (eps, MinPts) grid point."""
+    W = wl.sweep_32d()
+    X = torch.from_numpy(W.X).cuda()
+    m = sng.samples_per_point(W.s, W.n)
+    entry = {"workload": W.name, "grid": [len(W.eps_grid), len(W.min_pts_grid)],
+             "slots_per_pass": W.n * m}
+    lab, deg, ws = sng.dbscan(X, W.s, float(W.eps_grid[0]), 2, W.seed)
+    t_one = _cuda_ms(torch, lambda: sng.dbscan(X, W.s, float(W.eps_grid[5]), 4, W.seed,
+                                               labels=lab, degrees_out=deg, ws=ws), reps)
+    entry["plain_single_ms"] = t_one
+    entry["plain_all_pairs_ms_est"] = t_one * len(W.eps_grid) * len(W.min_pts_grid)
     try:
-        W = wl.mnistlike_784d()
-        X = torch.from_numpy(W.X).cuda()
-        Xlp = torch.from_numpy(W.X_lp.view(__import__("numpy").int16)).cuda()
-        m = sng.samples_per_point(W.s, W.n)
-        lab, deg, ws = sng.dbscan(X, W.s, W.eps, W.min_pts, W.seed)
-        t_plain = cuda_ms(lambda: sng.dbscan(X, W.s, W.eps, W.min_pts, W.seed, labels=lab,
-                                             degrees_out=deg, ws=ws))
-        entry = {"workload": W.name, "slots": W.n * m, "plain_ms": t_plain}
-        try:
-            lab2, deg2, ws2 = sng.dbscan_lowp(X, Xlp, W.s, W.eps, W.min_pts, W.seed)
-            t_mixed = cuda_ms(lambda: sng.dbscan_lowp(X, Xlp, W.s, W.eps, W.min_pts, W.seed,
-                                                      ws=ws2))
-            lab2, deg2, ws2 = sng.dbscan_lowp(X, Xlp, W.s, W.eps, W.min_pts, W.seed, ws=ws2)
-            torch.cuda.synchronize()
-            st = sng.stats(ws2)
-            entry.update({"mixed_bf16_ms": t_mixed, "speedup": t_plain / t_mixed,
-                          "labels_identical": bool(torch.equal(lab, lab2)),
-                          "degrees_identical": bool(torch.equal(deg, deg2)),
-                          "recheck_fraction": st.rechecked / max(1, st.slots),
-                          "band_rel": st.band_rel})
-        except sng.SNGError as e:
-            entry["mixed_bf16"] = "unavailable: %s" % e
-        out["mixed_precision"] = entry
-        del X, Xlp, ws
-    except Exception as e:  # the headline line must still print
-        out["mixed_precision"] = "error: %s" % e
+        sl, sd, sws = sng.sweep(X, W.s, W.eps_grid, W.min_pts_grid, W.seed)
+        t_sweep = _cuda_ms(torch, lambda: sng.sweep(X, W.s, W.eps_grid, W.min_pts_grid, W.seed,
+                                                    ws=sws), max(1, reps - 1))
+        entry.update({"sweep_ms": t_sweep,
+                      "speedup_vs_all_plain": entry["plain_all_pairs_ms_est"] / t_sweep})
+    except sng.SNGError as e:
+        entry["sweep"] = "unavailable: %s" % e
+    return entry
 
-    # one sweep pass versus one plain call per grid point
+
+def form_batch(sng, torch, wl, reps):
+    """64 uneven instances: sequential plain calls vs one captured-graph launch."""
+    B = wl.uneven_batch()
+    Xs = [torch.from_numpy(b.X).cuda() for b in B]
+    slots = sum(b.n * sng.samples_per_point(b.s, b.n) for b in B)
+    wss = [sng.dbscan(x, b.s, b.eps, b.min_pts, b.seed)[2] for x, b in zip(Xs, B)]
+
+    def seq():
+        for x, b, w in zip(Xs, B, wss):
+            sng.dbscan(x, b.s, b.eps, b.min_pts, b.seed, ws=w)
+    entry = {"instances": len(B), "slots": slots, "sequential_ms": _cuda_ms(torch, seq, reps)}
     try:
-        W = wl.sweep_32d()
-        X = torch.from_numpy(W.X).cuda()
-        m = sng.samples_per_point(W.s, W.n)
-        entry = {"workload": W.name, "grid": [len(W.eps_grid), len(W.min_pts_grid)],
-                 "slots_per_pass": W.n * m}
-        lab, deg, ws = sng.dbscan(X, W.s, float(W.eps_grid[0]), 2, W.seed)
-        t_one = cuda_ms(lambda: sng.dbscan(X, W.s, float(W.eps_grid[5]), 4, W.seed, labels=lab,
-                                           degrees_out=deg, ws=ws))
-        entry["plain_single_ms"] = t_one
-        entry["plain_all_pairs_ms_est"] = t_one * len(W.eps_grid) * len(W.min_pts_grid)
-        try:
-            sl, sd, sws = sng.sweep(X, W.s, W.eps_grid, W.min_pts_grid, W.seed)
-            t_sweep = cuda_ms(lambda: sng.sweep(X, W.s, W.eps_grid, W.min_pts_grid, W.seed,
-                                                ws=sws), 2)
-            entry.update({"sweep_ms": t_sweep,
-                          "speedup_vs_all_plain": entry["plain_all_pairs_ms_est"] / t_sweep})
-        except sng.SNGError as e:
-            entry["sweep"] = "unavailable: %s" % e
-        out["sweep"] = entry
-        del X, ws
-    except Exception as e:
-        out["sweep"] = "error: %s" % e
+        plan = sng.BatchPlan(Xs, [b.s for b in B], [b.eps for b in B],
+                             [b.min_pts for b in B], [b.seed for b in B])
+        t_graph = _cuda_ms(torch, lambda: plan.launch(), reps)
+        entry.update({"graph_batch_ms": t_graph, "speedup": entry["sequential_ms"] / t_graph})
+    except sng.SNGError as e:
+        entry["graph_batch"] = "unavailable: %s" % e
+    return entry
 
-    # 64 uneven instances: sequential plain calls versus one batched launch
-    try:
-        B = wl.uneven_batch()
-        Xs = [torch.from_numpy(b.X).cuda() for b in B]
-        slots = sum(b.n * sng.samples_per_point(b.s, b.n) for b in B)
-        wss = [sng.dbscan(x, b.s, b.eps, b.min_pts, b.seed)[2] for x, b in zip(Xs, B)]
 
-        def seq():
-            for x, b, w in zip(Xs, B, wss):
-                sng.dbscan(x, b.s, b.eps, b.min_pts, b.seed, ws=w)
-        entry = {"instances": len(B), "slots": slots, "sequential_ms": cuda_ms(seq)}
+FORMS = {"mixed": ("mixed_precision", form_mixed), "sweep": ("sweep", form_sweep),
+         "batch": ("batch", form_batch)}
+
+
+def time_forms(sng, torch, wl, which, reps=3):
+    out = {}
+    for name in which:
+        key, fn = FORMS[name]
         try:
-            plan = sng.BatchPlan(Xs, [b.s for b in B], [b.eps for b in B],
-                                 [b.min_pts for b in B], [b.seed for b in B])
-            t_graph = cuda_ms(lambda: plan.launch())
-            entry.update({"graph_batch_ms": t_graph, "speedup": entry["sequential_ms"] / t_graph})
-        except sng.SNGError as e:
-            entry["graph_batch"] = "unavailable: %s" % e
-        out["batch"] = entry
-    except Exception as e:
-        out["batch"] = "error: %s" % e
-    torch.cuda.empty_cache()
+            out[key] = fn(sng, torch, wl, reps)
+        except Exception as e:  # the headline line must still print
+            out[key] = "error: %s" % e
+        torch.cuda.empty_cache()
     return out
 
 
@@ -211,6 +216,8 @@ def main():
     ap.add_argument("--schedule", choices=["tuned", "auto", "direct"], default="tuned",
                     help="tuned: the autotuner's choice (timed before the run); auto: the "
                          "library's rule (partner blocks here); direct: direct gathers")
+    ap.add_argument("--forms", default="mixed,sweep,batch",
+                    help="comma-separated subset of mixed, sweep, batch")
     ap.add_argument("--no-forms", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -332,8 +339,12 @@ def main():
         torch.cuda.synchronize()
         out["calibration_copy_bytes"] = src.numel()
         del src, dst
-    if not args.no_forms:
-        out["forms"] = time_forms(sng, torch, wl)
+    forms = [f for f in args.forms.split(",") if f] if not args.no_forms else []
+    for f in forms:
+        if f not in FORMS:
+            raise SystemExit("bench.py: unknown form %r" % f)
+    if forms:
+        out["forms"] = time_forms(sng, torch, wl, forms)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(W, m)
     print(json.dumps(out), flush=True)

@@ -29,37 +29,45 @@ namespace sng {
 
 constexpr uint32_t kRecOffShift = 18;  // record: call offset (14 bits) | word (2) | partner (16)
 
+// Decisions take point indices; row pointers for the binary64 recheck are
+// formed only inside the band. record() receives the slot's global call
+// number as a functor, evaluated only for accepted slots.
 struct BucketPlainPolicy {
+    const float *X;
+    int64_t ld;
+    int d;
     uint32_t *deg;
     uint32_t *mask;
     float lo, hi;
     double eps2;
 
-    __device__ __forceinline__ int decide(float F, const float *rowi, const float *rowj, int d,
-                                          Tally &t, int q)
+    __device__ __forceinline__ int decide(float F, uint32_t i, uint32_t j, Tally &t, int q)
     {
         if (F <= lo)
             return 1;
         if (F > hi)
             return 0;
         t.rechecked += (q == 0);
-        return sqdist_f64(rowi, rowj, d) <= eps2;
+        return sqdist_f64(X + (int64_t)i * ld, X + (int64_t)j * ld, d) <= eps2;
     }
-    __device__ __forceinline__ void record(int acc, uint32_t i, uint32_t j, uint64_t call, int w,
+    template <class CallFn>
+    __device__ __forceinline__ void record(int acc, uint32_t i, uint32_t j, CallFn call_of, int w,
                                            int q, Tally &t)
     {
-        if (acc) {
-            if (q == 0) {
-                atomicAdd(deg + i, 1u);
-                atomicAdd(deg + j, 1u);
-                atomicOr(mask + (call >> 3), 1u << (4 * (call & 7) + w));
-                t.accepted += 1;
-            }
+        if (acc && q == 0) {
+            const uint64_t call = call_of();
+            atomicAdd(deg + i, 1u);
+            atomicAdd(deg + j, 1u);
+            atomicOr(mask + (call >> 3), 1u << (4 * (call & 7) + w));
+            t.accepted += 1;
         }
     }
 };
 
 struct BucketSweepPolicy {
+    const float *X;
+    int64_t ld;
+    int d;
     uint32_t *hist;
     uint8_t *codes;  // byte per slot (call*4 + word), pre-filled with K
     const float *lo;
@@ -68,8 +76,7 @@ struct BucketSweepPolicy {
     int K;
     float hi_max;
 
-    __device__ __forceinline__ int decide(float F, const float *rowi, const float *rowj, int d,
-                                          Tally &t, int q)
+    __device__ __forceinline__ int decide(float F, uint32_t i, uint32_t j, Tally &t, int q)
     {
         if (!(F <= hi_max))
             return K;
@@ -84,16 +91,18 @@ struct BucketSweepPolicy {
         if (F <= lo[a])
             return a;
         t.rechecked += (q == 0);
-        const double D = sqdist_f64(rowi, rowj, d);
+        const double D = sqdist_f64(X + (int64_t)i * ld, X + (int64_t)j * ld, d);
         int k = a;
         while (k < K && !(D <= e2[k]))
             ++k;
         return k;
     }
-    __device__ __forceinline__ void record(int b, uint32_t i, uint32_t j, uint64_t call, int w,
+    template <class CallFn>
+    __device__ __forceinline__ void record(int b, uint32_t i, uint32_t j, CallFn call_of, int w,
                                            int q, Tally &t)
     {
         if (b < K && q == 0) {
+            const uint64_t call = call_of();
             atomicAdd(hist + (uint64_t)i * K + b, 1u);
             atomicAdd(hist + (uint64_t)j * K + b, 1u);
             codes[call * 4ull + (uint64_t)w] = (uint8_t)b;
@@ -271,14 +280,7 @@ __device__ __forceinline__ bool sample_ok(const Inst &I, const BucketGeom &B)
 constexpr uint32_t kTicketRanges = 16;
 static_assert(kTicketRanges <= kWave, "one lane per segment of a ticket");
 
-__device__ __forceinline__ uint64_t readlane_u64(uint64_t v, int l)
-{
-    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
-    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), l);
-    return ((uint64_t)hi << 32) | lo;
-}
-
-template <class Row, int OB, class Pol>
+template <class Row, int OB, bool kBuf, class Pol>
 __device__ __forceinline__ void eval_ticket(const Inst &I, const BucketGeom &B, Pol &pol,
                                             uint64_t r0, uint32_t T, uint32_t J, Tally &tally)
 {
@@ -289,11 +291,14 @@ __device__ __forceinline__ void eval_ticket(const Inst &I, const BucketGeom &B, 
     const int lane = lane_id();
     const int q = lane & (G - 1);
     const int grp = lane / G;
-    uint32_t cnt_l = 0, i0_l = 0, c0_l = 0;
-    uint64_t base_l = 0;
+    // Records of the ticket: T consecutive regions of the record array, read
+    // through a buffer descriptor with 32-bit offsets.
+    const __amdgpu_buffer_rsrc_t rrec =
+        buf_rsrc(B.rec + r0 * B.region, (uint32_t)(T * B.region * sizeof(uint32_t)));
+    uint32_t cnt_l = 0, i0_l = 0, c0_l = 0, base_l = 0;
     if ((uint32_t)lane < T) {
         const uint64_t r = r0 + (uint64_t)lane;
-        base_l = r * B.region + B.seg[(r * B.NJ + J) * 2 + 0];
+        base_l = (uint32_t)lane * (uint32_t)B.region + B.seg[(r * B.NJ + J) * 2 + 0];
         cnt_l = B.seg[(r * B.NJ + J) * 2 + 1];
         i0_l = B.start[2 * r + 0];
         c0_l = B.start[2 * r + 1];
@@ -309,21 +314,23 @@ __device__ __forceinline__ void eval_ticket(const Inst &I, const BucketGeom &B, 
     const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)incl, kWave - 1);
     if (total == 0)
         return;  // wave-uniform
-    base_l -= excl_l;  // record f of segment l is B.rec[base_l + f]
+    // record f of segment l < T sits at index base_l + f of the ticket's
+    // records (no wrap: excl_l <= l * region)
+    base_l -= excl_l;
 
     // Loads the records of window [f0, f0 + kStep) and their segments.
     auto locate = [&](uint32_t f0, uint32_t (&vv)[P], uint32_t (&ss)[P]) {
         const int s_lo = __popcll(__ballot(excl_l <= f0)) - 1;
         const int s_hi = min(__popcll(__ballot(excl_l < f0 + kStep)), (int)T) - 1;
-        uint64_t bk[P];
+        uint32_t bk[P];
 #pragma unroll
         for (int k = 0; k < P; ++k) {
-            bk[k] = readlane_u64(base_l, s_lo);
+            bk[k] = (uint32_t)__builtin_amdgcn_readlane((int)base_l, s_lo);
             ss[k] = (uint32_t)s_lo;
         }
         for (int b = s_lo + 1; b <= s_hi; ++b) {  // wave-uniform
             const uint32_t e = (uint32_t)__builtin_amdgcn_readlane((int)excl_l, b);
-            const uint64_t bb = readlane_u64(base_l, b);
+            const uint32_t bb = (uint32_t)__builtin_amdgcn_readlane((int)base_l, b);
 #pragma unroll
             for (int k = 0; k < P; ++k) {
                 if (f0 + (uint32_t)(k * kGroups + grp) >= e) {
@@ -335,7 +342,9 @@ __device__ __forceinline__ void eval_ticket(const Inst &I, const BucketGeom &B, 
 #pragma unroll
         for (int k = 0; k < P; ++k) {
             const uint32_t f = f0 + (uint32_t)(k * kGroups + grp);
-            vv[k] = (f < total) ? B.rec[bk[k] + f] : 0u;
+            vv[k] = (f < total)
+                        ? __builtin_amdgcn_raw_buffer_load_b32(rrec, (int)((bk[k] + f) * 4u), 0, 0)
+                        : 0u;
         }
     };
 
@@ -343,6 +352,10 @@ __device__ __forceinline__ void eval_ticket(const Inst &I, const BucketGeom &B, 
     const float *__restrict__ X = I.X;
     const int64_t ld = I.ld;
     const int d = I.d;
+    const uint32_t ld4 = (uint32_t)ld * 4u;  // row stride in bytes (buffer form)
+    __amdgpu_buffer_rsrc_t rs;
+    if constexpr (kBuf)
+        rs = buf_rsrc(X, B.x_bytes);
     uint32_t nv[P], ns[P];
     locate(0, nv, ns);
     for (uint32_t f0 = 0; f0 < total; f0 += kStep) {  // wave-uniform
@@ -354,8 +367,7 @@ __device__ __forceinline__ void eval_ticket(const Inst &I, const BucketGeom &B, 
         }
         if (f0 + kStep < total)
             locate(f0 + kStep, nv, ns);
-        uint32_t ii[P], cj[P], ww[P];
-        uint64_t call[P];
+        uint32_t ii[P], cj[P];
         bool live[P];
         typename Row::Buf bi[P], bj[P];
 #pragma unroll
@@ -364,20 +376,17 @@ __device__ __forceinline__ void eval_ticket(const Inst &I, const BucketGeom &B, 
             const uint32_t i0 = (uint32_t)__shfl((int)i0_l, (int)sv[k]);
             const uint32_t c0 = (uint32_t)__shfl((int)c0_l, (int)sv[k]);
             const uint32_t co = v[k] >> kRecOffShift;
-            ww[k] = (v[k] >> 16) & 3u;
             cj[k] = jbase | (v[k] & 0xFFFFu);
-            uint32_t cc = c0 + co, i = i0;
-            if (cc >= I.C) {
-                const uint32_t qq = div_exact(cc, I.C, I.inv_C);
-                i += qq;
-                cc -= qq * I.C;
-            }
-            ii[k] = i;
-            call[k] = (r0 + sv[k]) * kRangeCalls + co;
+            ii[k] = i0 + div_magic(c0 + co, B.cdiv);
             const uint32_t sj = live[k] ? cj[k] : 0u;  // row 0 always exists
-            const uint32_t si = live[k] ? i : 0u;
-            bj[k] = Row::fetch(X + (int64_t)sj * ld, q, d);
-            bi[k] = Row::fetch(X + (int64_t)si * ld, q, d);
+            const uint32_t si = live[k] ? ii[k] : 0u;
+            if constexpr (kBuf) {
+                bj[k] = Row::fetchb(rs, __umul24(sj, ld4), q, d);
+                bi[k] = Row::fetchb(rs, __umul24(si, ld4), q, d);
+            } else {
+                bj[k] = Row::fetch(X + (int64_t)sj * ld, q, d);
+                bi[k] = Row::fetch(X + (int64_t)si * ld, q, d);
+            }
         }
 #pragma unroll
         for (int k = 0; k < P; ++k) {
@@ -385,9 +394,11 @@ __device__ __forceinline__ void eval_ticket(const Inst &I, const BucketGeom &B, 
                 continue;
             float F = group_sum<G>(Row::partial2(bi[k], bj[k], q, d));
             F = __int_as_float((int)group_bcast<G>((uint32_t)__float_as_int(F), 0));
-            const int res = pol.decide(F, X + (int64_t)ii[k] * ld, X + (int64_t)cj[k] * ld, d,
-                                       tally, q);
-            pol.record(res, ii[k], cj[k], call[k], (int)ww[k], q, tally);
+            const int res = pol.decide(F, ii[k], cj[k], tally, q);
+            const uint32_t vk = v[k], sk = sv[k];
+            pol.record(res, ii[k], cj[k],
+                       [&]() { return (r0 + sk) * kRangeCalls + (vk >> kRecOffShift); },
+                       (int)((vk >> 16) & 3u), q, tally);
         }
     }
 }
@@ -404,7 +415,7 @@ __device__ __forceinline__ uint32_t my_xcd()
 // stream in sequential pieces. Wavefronts then help the other queues until
 // all are empty, so every ticket is taken exactly once whichever XCDs the
 // workgroups land on.
-template <class Row, int OB, class Pol>
+template <class Row, int OB, bool kBuf, class Pol>
 __device__ __forceinline__ void eval_all(const Inst &I, const BucketGeom &B, Pol &pol,
                                          Tally &tally)
 {
@@ -415,38 +426,45 @@ __device__ __forceinline__ void eval_all(const Inst &I, const BucketGeom &B, Pol
         const uint64_t blocks = (B.NJ > x) ? (B.NJ - x + kXcds - 1) / kXcds : 0;
         const uint64_t total = blocks * tpj;
         for (;;) {
-            unsigned long long e = 0;
+            unsigned long long got = 0;
             if (lane_id() == 0)
-                e = atomicAdd(B.queue + x, 1ull);
-            e = __shfl(e, 0);
+                got = atomicAdd(B.queue + x, 1ull);
+            // lane 0's ticket, held in scalar registers (uniform to the compiler)
+            const uint64_t e =
+                ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(got >> 32))
+                 << 32) |
+                (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)got);
             if (e >= total)
                 break;  // wave-uniform
             const uint64_t jl = e / tpj;
             const uint64_t r0 = (e - jl * tpj) * kTicketRanges;
             const uint64_t left = B.ranges - r0;
             const uint32_t T = (uint32_t)(left < kTicketRanges ? left : kTicketRanges);
-            eval_ticket<Row, OB>(I, B, pol, r0, T, (uint32_t)(x + jl * kXcds), tally);
+            eval_ticket<Row, OB, kBuf>(I, B, pol, r0, T, (uint32_t)(x + jl * kXcds), tally);
         }
     }
 }
 
-template <class Row, int OB>
+template <class Row, int OB, bool kBuf>
 __global__ __launch_bounds__(256) void k_bkt_eval_plain(Inst I, BucketGeom B)
 {
     if (!sample_ok(I, B))
         return;
     BucketPlainPolicy pol;
+    pol.X = I.X;
+    pol.ld = I.ld;
+    pol.d = I.d;
     pol.deg = I.deg;
     pol.mask = I.mask;
     pol.lo = I.lo;
     pol.hi = I.hi;
     pol.eps2 = I.eps2;
     Tally t;
-    eval_all<Row, OB>(I, B, pol, t);
+    eval_all<Row, OB, kBuf>(I, B, pol, t);
     commit_tally(t, I.cnt);
 }
 
-template <class Row, int OB>
+template <class Row, int OB, bool kBuf>
 __global__ __launch_bounds__(256) void k_bkt_eval_sweep(Inst I, BucketGeom B, SweepArgs S)
 {
     if (!sample_ok(I, B))
@@ -460,6 +478,9 @@ __global__ __launch_bounds__(256) void k_bkt_eval_sweep(Inst I, BucketGeom B, Sw
     }
     __syncthreads();
     BucketSweepPolicy pol;
+    pol.X = I.X;
+    pol.ld = I.ld;
+    pol.d = I.d;
     pol.hist = S.hist;
     pol.codes = reinterpret_cast<uint8_t *>(S.codes);
     pol.lo = s_lo;
@@ -468,7 +489,7 @@ __global__ __launch_bounds__(256) void k_bkt_eval_sweep(Inst I, BucketGeom B, Sw
     pol.K = S.K;
     pol.hi_max = S.c.hi[S.K - 1];
     Tally t;
-    eval_all<Row, OB>(I, B, pol, t);
+    eval_all<Row, OB, kBuf>(I, B, pol, t);
     commit_tally(t, I.cnt);
 }
 
@@ -497,6 +518,11 @@ bool bucket_geometry(int64_t n, int d, int64_t m, bool force, BucketGeom *g)
     const uint64_t calls = (uint64_t)n * C;
     b.ranges = (calls + kRangeCalls - 1) / kRangeCalls;
     b.region = kRangeSlots;
+    uint32_t l = 0;
+    while (((uint64_t)1 << l) < C)
+        ++l;
+    b.cdiv.shift = 31 + l;
+    b.cdiv.m = (uint32_t)((((uint64_t)1 << (31 + l)) + C - 1) / C);
     if (g)
         *g = b;
     return true;
@@ -546,6 +572,16 @@ static hipError_t prepare_eval(const Inst &I, const BucketGeom &B, bool reuse, h
     return hipGetLastError();
 }
 
+// Rows are read through a buffer descriptor with 32-bit byte offsets formed
+// by 24-bit multiplies when X spans less than 4 GB, the row index fits 24
+// bits and the row stride in bytes fits 24 bits.
+static bool use_buffer(const Inst &I)
+{
+    const uint64_t bytes = (uint64_t)I.n * (uint64_t)I.ld * 4u;
+    return bytes < ((uint64_t)1 << 32) - 4096 && I.n < (1u << 24) &&
+           (uint64_t)I.ld * 4u < ((uint64_t)1 << 24);
+}
+
 static unsigned eval_blocks(const BucketGeom &B)
 {
     // 128 blocks of 4 waves per XCD (four per CU), a multiple of kXcds
@@ -553,17 +589,31 @@ static unsigned eval_blocks(const BucketGeom &B)
     return kXcds * 128;
 }
 
-hipError_t launch_bucket_plain(const Inst &I, const BucketGeom &B, const PassAShape &sh,
+// The geometry as the evaluate kernels take it: with the byte span of X for
+// the buffer form.
+static BucketGeom eval_geom(const Inst &I, const BucketGeom &B)
+{
+    BucketGeom g = B;
+    g.x_bytes = use_buffer(I) ? (uint32_t)((uint64_t)I.n * (uint64_t)I.ld * 4u) : 0u;
+    return g;
+}
+
+hipError_t launch_bucket_plain(const Inst &I, const BucketGeom &B0, const PassAShape &sh,
                                bool reuse, hipStream_t st)
 {
+    const BucketGeom B = eval_geom(I, B0);
     hipError_t e = prepare_eval(I, B, reuse, st);
     if (e != hipSuccess)
         return e;
     const bool vec_ok = ((uintptr_t)I.X % 16 == 0) && (I.ld % 4 == 0);
     return dispatch(I.d, vec_ok, sh, [&]<class Row, int OB>(uint32_t) -> hipError_t {
         if constexpr (Row::kPrefetch) {
-            hipLaunchKernelGGL((k_bkt_eval_plain<Row, OB>), dim3(eval_blocks(B)), dim3(256), 0, st,
-                               I, B);
+            if (use_buffer(I))
+                hipLaunchKernelGGL((k_bkt_eval_plain<Row, OB, true>), dim3(eval_blocks(B)),
+                                   dim3(256), 0, st, I, B);
+            else
+                hipLaunchKernelGGL((k_bkt_eval_plain<Row, OB, false>), dim3(eval_blocks(B)),
+                                   dim3(256), 0, st, I, B);
             return hipGetLastError();
         } else {
             return hipErrorInvalidValue;
@@ -571,17 +621,22 @@ hipError_t launch_bucket_plain(const Inst &I, const BucketGeom &B, const PassASh
     });
 }
 
-hipError_t launch_bucket_sweep(const Inst &I, const SweepArgs &S, const BucketGeom &B,
+hipError_t launch_bucket_sweep(const Inst &I, const SweepArgs &S, const BucketGeom &B0,
                                const PassAShape &sh, hipStream_t st)
 {
+    const BucketGeom B = eval_geom(I, B0);
     hipError_t e = prepare_eval(I, B, false, st);
     if (e != hipSuccess)
         return e;
     const bool vec_ok = ((uintptr_t)I.X % 16 == 0) && (I.ld % 4 == 0);
     return dispatch(I.d, vec_ok, sh, [&]<class Row, int OB>(uint32_t) -> hipError_t {
         if constexpr (Row::kPrefetch) {
-            hipLaunchKernelGGL((k_bkt_eval_sweep<Row, OB>), dim3(eval_blocks(B)), dim3(256), 0, st,
-                               I, B, S);
+            if (use_buffer(I))
+                hipLaunchKernelGGL((k_bkt_eval_sweep<Row, OB, true>), dim3(eval_blocks(B)),
+                                   dim3(256), 0, st, I, B, S);
+            else
+                hipLaunchKernelGGL((k_bkt_eval_sweep<Row, OB, false>), dim3(eval_blocks(B)),
+                                   dim3(256), 0, st, I, B, S);
             return hipGetLastError();
         } else {
             return hipErrorInvalidValue;

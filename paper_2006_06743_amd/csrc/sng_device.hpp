@@ -95,6 +95,35 @@ __device__ __forceinline__ uint32_t mod_exact(uint32_t w, uint32_t n, double inv
     return (uint32_t)r;
 }
 
+// floor(a / C) for a < 2^31 by multiply and shift (Granlund and Montgomery,
+// PLDI 1994, Thm 4.2 with N = 31): with l = ceil(log2 C) and
+// m = ceil(2^(31+l) / C) < 2^32, floor(a / C) = floor(a * m / 2^(31+l)).
+struct DivMagic {
+    uint32_t m;
+    uint32_t shift;  // 31 + l
+};
+__device__ __forceinline__ uint32_t div_magic(uint32_t a, DivMagic dm)
+{
+    return (uint32_t)(((uint64_t)a * dm.m) >> dm.shift);
+}
+
+// Raw buffer access: 32-bit byte offsets from a base address; offsets at or
+// past `bytes` read as zero.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void *base, uint32_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), 0, (int)bytes, 0x00020000);
+}
+__device__ __forceinline__ float bld1(__amdgpu_buffer_rsrc_t r, uint32_t off)
+{
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0));
+}
+__device__ __forceinline__ float4 bld4(__amdgpu_buffer_rsrc_t r, uint32_t off)
+{
+    const auto v = __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, 0);
+    return make_float4(__uint_as_float(v[0]), __uint_as_float(v[1]), __uint_as_float(v[2]),
+                       __uint_as_float(v[3]));
+}
+
 // Exact floor division a / b for a, b < 2^32 (same argument as mod_exact).
 __device__ __forceinline__ uint32_t div_exact(uint32_t a, uint32_t b, double inv_b)
 {

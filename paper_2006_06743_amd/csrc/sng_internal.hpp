@@ -90,6 +90,8 @@ struct BucketGeom {
     unsigned long long *queue;  // [kXcds] next ticket of each XCD's queue
     unsigned long long *hdr;    // [2] tag of the sample held in rec, and its self-pair count
     uint64_t tag;               // tag of the sample these arguments describe (never 0)
+    DivMagic cdiv;              // division by ceil(m/4), the calls per point
+    uint32_t x_bytes;           // bytes of X addressed through the buffer descriptor
 };
 // u64 index of BucketGeom::hdr inside an instance's counter header
 constexpr int kSampleHdr = 32;

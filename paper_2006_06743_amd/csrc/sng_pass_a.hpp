@@ -29,6 +29,26 @@ struct SmallRow {
             b.v[k] = row[k];
         return b;
     }
+    // The same from a buffer: row at byte offset `off`.
+    __device__ __forceinline__ static Buf fetchb(__amdgpu_buffer_rsrc_t rs, uint32_t off, int, int)
+    {
+        Buf b;
+        if constexpr (D == 3) {
+            const auto v = __builtin_amdgcn_raw_buffer_load_b96(rs, (int)off, 0, 0);
+            b.v[0] = __uint_as_float(v[0]);
+            b.v[1] = __uint_as_float(v[1]);
+            b.v[2] = __uint_as_float(v[2]);
+        } else if constexpr (D == 2) {
+            const auto v = __builtin_amdgcn_raw_buffer_load_b64(rs, (int)off, 0, 0);
+            b.v[0] = __uint_as_float(v[0]);
+            b.v[1] = __uint_as_float(v[1]);
+        } else {
+#pragma unroll
+            for (int k = 0; k < D; ++k)
+                b.v[k] = bld1(rs, off + 4u * k);
+        }
+        return b;
+    }
     __device__ __forceinline__ void load(const float *row, int q, int d, float *)
     {
         r = fetch(row, q, d);
@@ -67,6 +87,20 @@ struct VecRow {
             const int k = 4 * (v * G + q);
             if (FULL || k < d)
                 b.v[v] = *reinterpret_cast<const float4 *>(row + k);
+            else
+                b.v[v] = make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+        return b;
+    }
+    __device__ __forceinline__ static Buf fetchb(__amdgpu_buffer_rsrc_t rs, uint32_t off, int q,
+                                                 int d)
+    {
+        Buf b;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            const int k = 4 * (v * G + q);
+            if (FULL || k < d)
+                b.v[v] = bld4(rs, off + 4u * (uint32_t)k);
             else
                 b.v[v] = make_float4(0.f, 0.f, 0.f, 0.f);
         }
@@ -116,6 +150,17 @@ struct ScalarRow {
         for (int v = 0; v < NS; ++v) {
             const int k = v * G + q;
             b.v[v] = (k < d) ? row[k] : 0.0f;
+        }
+        return b;
+    }
+    __device__ __forceinline__ static Buf fetchb(__amdgpu_buffer_rsrc_t rs, uint32_t off, int q,
+                                                 int d)
+    {
+        Buf b;
+#pragma unroll
+        for (int v = 0; v < NS; ++v) {
+            const int k = v * G + q;
+            b.v[v] = (k < d) ? bld1(rs, off + 4u * (uint32_t)k) : 0.0f;
         }
         return b;
     }
