@@ -77,12 +77,18 @@ __device__ __forceinline__ void b_hook_pair(const Inst &I, uint32_t a, uint32_t 
         atomicMin(I.labels + a, (int32_t)b);
 }
 
+// Grid: total_wblocks rounded up to whole eighths; each XCD hooks a
+// contiguous eighth of the word blocks (xcd_block), so an instance's labels
+// and core flags stay in one L2.
 __global__ __launch_bounds__(256) void k_b_hook(const Inst *__restrict__ T, const BatchGeom G)
 {
-    const int k = block_instance(G.wblk, G.count, blockIdx.x);
+    const uint32_t blk = xcd_block(blockIdx.x, gridDim.x);
+    if (blk >= G.total_wblocks)
+        return;
+    const int k = block_instance(G.wblk, G.count, blk);
     const Inst &I = T[k];
     const uint64_t words = I.chunks * 8ull;
-    const uint64_t lo = (blockIdx.x - G.wblk[k]) * kWordsPerBlock;
+    const uint64_t lo = (blk - G.wblk[k]) * kWordsPerBlock;
     const uint64_t hi = umin64(lo + kWordsPerBlock, words);
     for (uint64_t w = lo + threadIdx.x; w < hi; w += blockDim.x) {
         const uint32_t bits = I.mask[I.chunk0 * 8ull + w];
@@ -161,7 +167,7 @@ hipError_t launch_batch(const Inst *T, const BatchGeom &G, int d, bool vec_ok,
     if ((e = hipGetLastError()) != hipSuccess)
         return e;
     if (wb > 0) {
-        hipLaunchKernelGGL(k_b_hook, dim3(wb), dim3(256), 0, st, T, G);
+        hipLaunchKernelGGL(k_b_hook, dim3((wb + 7) / 8 * 8), dim3(256), 0, st, T, G);
         if ((e = hipGetLastError()) != hipSuccess)
             return e;
     }

@@ -124,6 +124,16 @@ __device__ __forceinline__ float4 bld4(__amdgpu_buffer_rsrc_t r, uint32_t off)
                        __uint_as_float(v[3]));
 }
 
+// Logical block of a grid whose size is a multiple of 8: workgroup b is
+// dispatched to XCD b mod 8, so XCD x gets the logical blocks
+// [x * nb / 8, (x + 1) * nb / 8), a contiguous eighth of the work, taken in
+// order. Any dispatch order gives the same results; this one keeps each
+// XCD's data in its own L2.
+__device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t nb)
+{
+    return (b % 8u) * (nb / 8u) + b / 8u;
+}
+
 // Exact floor division a / b for a, b < 2^32 (same argument as mod_exact).
 __device__ __forceinline__ uint32_t div_exact(uint32_t a, uint32_t b, double inv_b)
 {
