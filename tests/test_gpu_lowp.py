@@ -52,17 +52,37 @@ def bits_for(X, prec, scale=1.0):
     return wl.bf16_bits(Y) if prec == 1 else wl.fp16_bits(Y)
 
 
+@pytest.fixture(scope="module")
+def mnist_ref(orc):
+    """The 70,000 x 784 workload and the oracle's result on it (computed once)."""
+    W = wl.mnistlike_784d()
+    return W, orc.dbscan(W.X, W.eps, W.min_pts, W.seed, s=W.s)
+
+
 @pytest.mark.timeout(600)
 @pytest.mark.parametrize("prec", [1, 2], ids=["bf16", "fp16"])
-def test_mnistlike_784d_full(sng, orc, prec):
-    W = wl.mnistlike_784d()
+def test_mnistlike_784d_full(sng, mnist_ref, prec):
+    W, ref = mnist_ref
     print("case", W.name, "prec", prec, flush=True)
-    ref = orc.dbscan(W.X, W.eps, W.min_pts, W.seed, s=W.s)
     gl, gd, st = run_lowp(sng, W.X, bits_for(W.X, prec), W.s, W.eps, W.min_pts, W.seed, prec)
     assert_same(gl, gd, ref, "%s prec=%d" % (W.name, prec))
     assert st.accepted == ref.accepted and st.n_clusters == ref.n_clusters
     print("rechecked fraction %.5f" % (st.rechecked / st.slots), flush=True)
     assert 0 < st.rechecked < 0.05 * st.slots
+
+
+@pytest.mark.timeout(600)
+def test_mnistlike_784d_full_plain(sng, mnist_ref):
+    """The plain binary32 path (the baseline the mixed form is timed against)
+    on the same workload: identical to the oracle too."""
+    import torch
+    W, ref = mnist_ref
+    Xg = torch.from_numpy(np.ascontiguousarray(W.X)).cuda()
+    lab, deg, ws = sng.dbscan(Xg, W.s, W.eps, W.min_pts, W.seed)
+    torch.cuda.synchronize()
+    st = sng.stats(ws)
+    assert_same(lab.cpu().numpy(), deg.cpu().numpy().view(np.uint32), ref, W.name + " plain")
+    assert st.accepted == ref.accepted
 
 
 def test_mnistlike_integer_copy(sng, orc):

@@ -208,6 +208,21 @@ def test_mixture16d_full_size(sng, orc, sigma):
     assert st.accepted == ref.accepted and st.n_clusters == ref.n_clusters
 
 
+@pytest.mark.timeout(900)
+def test_lidar3d_full_size(sng, orc):
+    """The 5e6-point LiDAR scene (1.25e10 slots) with both schedules of the
+    sampled-distance pass against one oracle run."""
+    W = wl.lidar_3d()
+    print("oracle", W.name, flush=True)
+    ref = orc.dbscan(W.X, W.eps, W.min_pts, W.seed, s=W.s)
+    for sched in (1, 2):
+        print("case", W.name, "schedule", sched, flush=True)
+        gl, gd, st = run(sng, W.X, W.s, W.eps, W.min_pts, W.seed, cfg=sng.Config(schedule=sched))
+        assert_same(gl, gd, ref, "%s schedule %d" % (W.name, sched))
+        assert st.accepted == ref.accepted and st.self_pairs == ref.self_pairs
+        assert st.n_clusters == ref.n_clusters
+
+
 def test_cluster_entry_point_many_minpts(sng, orc):
     """One sampled-distance pass, then post-processing for several MinPts."""
     import torch
