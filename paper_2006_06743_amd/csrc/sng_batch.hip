@@ -122,7 +122,7 @@ __global__ __launch_bounds__(256) void k_b_compress(const Inst *__restrict__ T, 
     uint32_t roots = 0;
     for (uint64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
         if (I.core[i]) {
-            const int32_t r = uf_find(I.labels, (int32_t)i);
+            const int32_t r = uf_root(I.labels, (int32_t)i);
             st_relaxed(I.labels + i, r);
             roots += (r == (int32_t)i);
         }

@@ -303,6 +303,20 @@ __device__ __forceinline__ int32_t uf_find(int32_t *P, int32_t x)
     return x;
 }
 
+// Root of x without writing anything. Used once the forest is final, when
+// each entry is rewritten only by its own thread: a walk that halved paths
+// could store an intermediate ancestor into an entry after that entry's own
+// thread had stored the root.
+__device__ __forceinline__ int32_t uf_root(const int32_t *P, int32_t x)
+{
+    int32_t p = ld_relaxed(P + x);
+    while (p != x) {
+        x = p;
+        p = ld_relaxed(P + x);
+    }
+    return x;
+}
+
 // Join the components of a and b: the larger root is hooked under the
 // smaller one by compare-and-swap, retrying from the new roots on conflict.
 __device__ __forceinline__ void uf_unite(int32_t *P, int32_t a, int32_t b)

@@ -146,7 +146,7 @@ __global__ __launch_bounds__(256) void k_compress(Inst I)
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < I.n;
          i += (uint64_t)gridDim.x * blockDim.x) {
         if (I.core[i]) {
-            const int32_t r = uf_find(I.labels, (int32_t)i);
+            const int32_t r = uf_root(I.labels, (int32_t)i);
             st_relaxed(I.labels + i, r);
             roots += (r == (int32_t)i);
         }

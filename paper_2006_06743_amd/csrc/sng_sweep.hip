@@ -192,7 +192,7 @@ __global__ __launch_bounds__(256) void k_sweep_compress(Inst I, SweepArgs S)
         const int p = (int)(pk / S.K), k = (int)(pk - (uint64_t)p * S.K);
         if (S.kc[(uint64_t)p * I.n + x] <= k) {
             int32_t *L = level_labels(S, I.n, p, k);
-            st_relaxed(L + x, uf_find(L, (int32_t)x));
+            st_relaxed(L + x, uf_root(L, (int32_t)x));
         }
     }
 }

@@ -346,3 +346,33 @@ def test_autotune_and_tuned_calls(sng, orc, n, d, s):
     assert_same(lab.cpu().numpy(), deg.cpu().numpy().view(np.uint32), ref, "direct-sized ws")
     sng.autotune_clear()
     assert sng.autotune_lookup(Xg, m) is None
+
+
+def test_graph_deep_forests(sng):
+    """Long paths hooked in random edge order build deep union-find trees;
+    every core label must still be its component's minimum index (the final
+    compression must not leave an intermediate ancestor behind)."""
+    import torch
+    rng = np.random.default_rng(99)
+    n = 300_000
+    perm = rng.permutation(n).astype(np.int64)
+    edges = np.stack([perm[:-1], perm[1:]], 1)
+    keep = np.ones(n - 1, bool)
+    keep[rng.choice(n - 1, 2, replace=False)] = False  # three paths
+    edges = edges[keep]
+    rng.shuffle(edges)
+    # expected: each path is one cluster named by its minimum point
+    comp = np.cumsum(np.r_[0, ~keep].astype(np.int64))  # path id along perm
+    first = np.full(comp.max() + 1, n, np.int64)
+    np.minimum.at(first, comp, perm)
+    want = np.empty(n, np.int64)
+    want[perm] = first[comp]
+    sizes = np.bincount(comp)
+    want[perm[sizes[comp] < 2]] = -1  # a one-point path has no edge: noise
+    for rep in range(3):
+        print("deep forest rep", rep, flush=True)
+        labels, deg, ws = sng.graph_labels(n, torch.from_numpy(edges.astype(np.int32)).cuda(), 1)
+        torch.cuda.synchronize()
+        got = labels.cpu().numpy()
+        bad = np.nonzero(got != want)[0]
+        assert bad.size == 0, "%d labels differ (first %s)" % (bad.size, bad[:5])
