@@ -254,6 +254,8 @@ int sng_batch_plan_create(int32_t count, const float *const *X, const int64_t *n
                           uint32_t *const *degrees, void *workspace, size_t ws_bytes,
                           void *stream, sng_batch_plan **plan);
 int sng_batch_plan_launch(sng_batch_plan *plan, void *stream);
+/* Releases the plan (always freed; NULL is a no-op). SNG_EHIP if releasing
+ * one of its HIP graph or stream handles failed. */
 int sng_batch_plan_destroy(sng_batch_plan *plan);
 
 /* Copies the counters of the last call that used `workspace` (waits for

@@ -1010,14 +1010,16 @@ int sng_batch_plan_destroy(sng_batch_plan *plan)
 {
     if (!plan)
         return SNG_OK;
-    if (plan->exec)
-        hipGraphExecDestroy(plan->exec);
-    if (plan->graph)
-        hipGraphDestroy(plan->graph);
-    if (plan->capture)
-        hipStreamDestroy(plan->capture);
+    // Teardown is best effort: each handle is released even if another fails.
+    hipError_t e = hipSuccess, x;
+    if (plan->exec && (x = hipGraphExecDestroy(plan->exec)) != hipSuccess)
+        e = x;
+    if (plan->graph && (x = hipGraphDestroy(plan->graph)) != hipSuccess)
+        e = x;
+    if (plan->capture && (x = hipStreamDestroy(plan->capture)) != hipSuccess)
+        e = x;
     delete plan;
-    return SNG_OK;
+    return e == hipSuccess ? SNG_OK : SNG_EHIP;
 }
 
 int sng_stats_read(const void *workspace, int32_t index, sng_stats *out, void *stream)
