@@ -77,39 +77,48 @@ __device__ __forceinline__ void b_hook_pair(const Inst &I, uint32_t a, uint32_t 
         atomicMin(I.labels + a, (int32_t)b);
 }
 
+// Hook of the accept words of one instance range, with block-local
+// compaction: a round scans 256 words (one per thread) and lists the
+// accepted slots in LDS, then all threads regenerate and hook them. Entry:
+// word offset in the round * 32 + bit (call in the word * 4 + Philox word).
+constexpr uint32_t kBHookWords = 256;
+
 // Grid: total_wblocks rounded up to whole eighths; each XCD hooks a
 // contiguous eighth of the word blocks (xcd_block), so an instance's labels
 // and core flags stay in one L2.
 __global__ __launch_bounds__(256) void k_b_hook(const Inst *__restrict__ T, const BatchGeom G)
 {
+    __shared__ uint16_t list[kBHookWords * 32];
+    __shared__ uint32_t nlist;
     const uint32_t blk = xcd_block(blockIdx.x, gridDim.x);
     if (blk >= G.total_wblocks)
-        return;
+        return;  // block-uniform
     const int k = block_instance(G.wblk, G.count, blk);
     const Inst &I = T[k];
     const uint64_t words = I.chunks * 8ull;
     const uint64_t lo = (blk - G.wblk[k]) * kWordsPerBlock;
     const uint64_t hi = umin64(lo + kWordsPerBlock, words);
-    for (uint64_t w = lo + threadIdx.x; w < hi; w += blockDim.x) {
-        const uint32_t bits = I.mask[I.chunk0 * 8ull + w];
-        if (bits == 0)
-            continue;
-        const uint64_t call0 = w * 8ull;
-        uint32_t i = (uint32_t)(call0 / I.C);
-        uint32_t c = (uint32_t)(call0 - (uint64_t)i * I.C);
-        for (int q = 0; q < 8; ++q) {
-            const uint32_t nib = (bits >> (4 * q)) & 0xFu;
-            if (nib) {
-                const Words4 W = philox10(c, i, I.key0, I.key1);
-                for (int t = 0; t < 4; ++t)
-                    if (nib & (1u << t))
-                        b_hook_pair(I, i, mod_exact(W.w[t], I.n, I.inv_n));
-            }
-            if (++c == I.C) {
-                c = 0;
-                ++i;
-            }
+    for (uint64_t w0 = lo; w0 < hi; w0 += kBHookWords) {  // block-uniform
+        if (threadIdx.x == 0)
+            nlist = 0;
+        const uint64_t w = w0 + threadIdx.x;
+        const uint32_t bits = (w < hi) ? I.mask[I.chunk0 * 8ull + w] : 0u;
+        if (!__syncthreads_or(bits != 0u))
+            continue;  // no accepted slot in this round (the list is not read)
+        uint32_t pos = list_reserve((uint32_t)__builtin_popcount(bits), &nlist);
+        for (uint32_t b = bits; b; b &= b - 1)
+            list[pos++] = (uint16_t)(threadIdx.x * 32u + (uint32_t)__builtin_ctz(b));
+        __syncthreads();
+        const uint32_t cnt = nlist;
+        for (uint32_t e = threadIdx.x; e < cnt; e += blockDim.x) {
+            const uint32_t v = list[e];
+            const uint64_t call = (w0 + (v >> 5)) * 8ull + ((v & 31u) >> 2);
+            const uint32_t i = (uint32_t)div_exact64(call, I.C, I.inv_C);
+            const uint32_t c = (uint32_t)(call - (uint64_t)i * I.C);
+            const Words4 W = philox10(c, i, I.key0, I.key1);
+            b_hook_pair(I, i, mod_exact(W.w[v & 3u], I.n, I.inv_n));
         }
+        __syncthreads();  // the next round reuses the list
     }
 }
 

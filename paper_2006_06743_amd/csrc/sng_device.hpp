@@ -95,6 +95,38 @@ __device__ __forceinline__ uint32_t mod_exact(uint32_t w, uint32_t n, double inv
     return (uint32_t)r;
 }
 
+// Exact floor division a / b for a < 2^40 and 1 <= b < 2^32: the binary64
+// estimate of a / b is within one of the quotient, then corrected.
+__device__ __forceinline__ uint64_t div_exact64(uint64_t a, uint32_t b, double inv_b)
+{
+    uint64_t q = (uint64_t)((double)a * inv_b);
+    const int64_t r = (int64_t)a - (int64_t)(q * (uint64_t)b);
+    if (r < 0)
+        q -= 1;
+    else if (r >= (int64_t)b)
+        q += 1;
+    return q;
+}
+
+// Space for `n` items in a workgroup-shared list: one LDS atomic per
+// wavefront (lanes may ask for zero). Returns this lane's first index.
+__device__ __forceinline__ uint32_t list_reserve(uint32_t n, uint32_t *count)
+{
+    uint32_t incl = n;
+#pragma unroll
+    for (int s = 1; s < 64; s <<= 1) {
+        const uint32_t u = __shfl_up(incl, s);
+        if ((int)__lane_id() >= s)
+            incl += u;
+    }
+    const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
+    uint32_t base = 0;
+    if (__lane_id() == 63 && total)
+        base = atomicAdd(count, total);
+    base = (uint32_t)__shfl((int)base, 63);
+    return base + incl - n;
+}
+
 // floor(a / C) for a < 2^31 by multiply and shift (Granlund and Montgomery,
 // PLDI 1994, Thm 4.2 with N = 31): with l = ceil(log2 C) and
 // m = ceil(2^(31+l) / C) < 2^32, floor(a / C) = floor(a * m / 2^(31+l)).

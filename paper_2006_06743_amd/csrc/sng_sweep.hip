@@ -133,28 +133,63 @@ __global__ __launch_bounds__(256) void k_sweep_levels(Inst I, SweepArgs S)
     }
 }
 
-// One thread per Philox call: regenerate the partners of its accepted slots.
+// Level hook with block-local compaction: a round scans kSweepHookCalls
+// calls' level codes (four calls per thread, coalesced), lists the slots
+// with a level below K in LDS, then every thread takes listed slots and
+// regenerates their partners. Entry: call offset in the round (10 bits) << 8
+// | Philox word << 6 | level.
+constexpr uint32_t kSweepHookCalls = 1024;
+
 __global__ __launch_bounds__(256) void k_sweep_hook(Inst I, SweepArgs S)
 {
-    for (uint64_t call = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; call < I.calls;
-         call += (uint64_t)gridDim.x * blockDim.x) {
-        const uint32_t word = S.codes[call];
-        if (word == 0x01010101u * (uint32_t)S.K)
+    __shared__ uint32_t list[4 * kSweepHookCalls];
+    __shared__ uint32_t nlist;
+    const uint32_t none = 0x01010101u * (uint32_t)S.K;
+    for (uint64_t c0 = (uint64_t)blockIdx.x * kSweepHookCalls; c0 < I.calls;
+         c0 += (uint64_t)gridDim.x * kSweepHookCalls) {  // block-uniform
+        if (threadIdx.x == 0)
+            nlist = 0;
+        uint32_t words[kSweepHookCalls / 256];
+        uint32_t n = 0;
+#pragma unroll
+        for (int r = 0; r < (int)(kSweepHookCalls / 256); ++r) {
+            const uint64_t call = c0 + (uint64_t)r * 256u + threadIdx.x;
+            words[r] = (call < I.calls) ? S.codes[call] : none;
+#pragma unroll
+            for (int w = 0; w < 4; ++w)
+                n += ((words[r] >> (8 * w)) & 0xFFu) < (uint32_t)S.K;
+        }
+        // the barrier also publishes the reset count; a round without listed
+        // slots is skipped (nothing reads the list)
+        if (!__syncthreads_or(n != 0u))
             continue;
-        const uint32_t i = (uint32_t)(call / I.C);
-        const uint32_t c = (uint32_t)(call - (uint64_t)i * I.C);
-        const Words4 W = philox10(c, i, I.key0, I.key1);
-        for (int w = 0; w < 4; ++w) {
-            const int b = (word >> (8 * w)) & 0xFF;
-            if (b >= S.K)
-                continue;
+        uint32_t pos = list_reserve(n, &nlist);
+#pragma unroll
+        for (int r = 0; r < (int)(kSweepHookCalls / 256); ++r) {
+#pragma unroll
+            for (int w = 0; w < 4; ++w) {
+                const uint32_t b = (words[r] >> (8 * w)) & 0xFFu;
+                if (b < (uint32_t)S.K)
+                    list[pos++] = ((r * 256u + threadIdx.x) << 8) | ((uint32_t)w << 6) | b;
+            }
+        }
+        __syncthreads();
+        const uint32_t cnt = nlist;
+        for (uint32_t e = threadIdx.x; e < cnt; e += blockDim.x) {
+            const uint32_t v = list[e];
+            const uint64_t call = c0 + (v >> 8);
+            const int w = (int)((v >> 6) & 3u);
+            const int b = (int)(v & 63u);
+            const uint32_t i = (uint32_t)div_exact64(call, I.C, I.inv_C);
+            const uint32_t c = (uint32_t)(call - (uint64_t)i * I.C);
+            const Words4 W = philox10(c, i, I.key0, I.key1);
             const uint32_t j = mod_exact(W.w[w], I.n, I.inv_n);
             for (int p = 0; p < S.P; ++p) {
                 const int ki = S.kc[(uint64_t)p * I.n + i];
                 const int kj = S.kc[(uint64_t)p * I.n + j];
-                const int e = max(b, max(ki, kj));
-                if (e < S.K)
-                    uf_unite(level_labels(S, I.n, p, e), (int32_t)i, (int32_t)j);
+                const int lev = max(b, max(ki, kj));
+                if (lev < S.K)
+                    uf_unite(level_labels(S, I.n, p, lev), (int32_t)i, (int32_t)j);
                 const int ei = max(b, ki);  // i is a core neighbour of j from ei on
                 if (ei < kj)
                     atomicMin(level_labels(S, I.n, p, ei) + j, (int32_t)i);
@@ -163,6 +198,7 @@ __global__ __launch_bounds__(256) void k_sweep_hook(Inst I, SweepArgs S)
                     atomicMin(level_labels(S, I.n, p, ej) + i, (int32_t)j);
             }
         }
+        __syncthreads();  // the next round reuses the list
     }
 }
 
