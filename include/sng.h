@@ -94,9 +94,11 @@ typedef struct {
  * with schedule 1 or stage_lds): skip drawing the partners and evaluate the
  * partner-block sample already in the workspace, as left by sng_sample or by
  * an earlier partner-block call with the same n, d, m and seed (any X of
- * that shape, any eps). The kernels check a tag stored with the sample; a
- * missing or different sample does no work and makes sng_stats_read report
- * SNG_EOVERFLOW. */
+ * that shape, any eps). The kernels check a tag stored with the sample (it
+ * names n, m, seed, block size and workspace layout; calls with other
+ * layouts clear it); a missing or different sample does no work and makes
+ * sng_stats_read report SNG_EOVERFLOW, and every decoded index is range
+ * checked as well. */
 
 /* Flag for sng_workspace_size: size for the direct schedule only (smaller;
  * a workspace of that size makes the automatic schedule choose it). */

@@ -166,18 +166,26 @@ int check_cfg(const sng_config *cfg)
     return SNG_OK;
 }
 
-__global__ void k_header(unsigned long long *cnt, unsigned long long slots, double band)
+__global__ void k_header(unsigned long long *cnt, unsigned long long slots, double band,
+                         int keep_sample)
 {
     const int t = threadIdx.x;
     if (t < kCntNum)
         cnt[t] = (t == kCntSlots) ? slots : 0ull;
     if (t == 0)
         ((double *)(cnt + kCntNum))[0] = band;
+    if (!keep_sample && t < 2)
+        cnt[kSampleHdr + t] = 0ull;  // this layout holds no partner-block sample
 }
 
-hipError_t init_header(unsigned long long *cnt, uint64_t slots, double band, hipStream_t st)
+// Counters of a call. keep_sample: the call uses the plain layout, so a
+// partner-block sample stored by an earlier call stays valid; every other
+// layout overwrites the record area and clears the sample's tag.
+hipError_t init_header(unsigned long long *cnt, uint64_t slots, double band, hipStream_t st,
+                       bool keep_sample = false)
 {
-    hipLaunchKernelGGL(k_header, dim3(1), dim3(64), 0, st, cnt, (unsigned long long)slots, band);
+    hipLaunchKernelGGL(k_header, dim3(1), dim3(64), 0, st, cnt, (unsigned long long)slots, band,
+                       keep_sample ? 1 : 0);
     return hipGetLastError();
 }
 
@@ -240,7 +248,7 @@ const sng_config *effective_cfg(const Inst &I, const sng_config *cfg, sng_config
 // schedule when it applies, the caller allows it and the workspace holds its
 // records (carved after `used` bytes); otherwise direct gathers.
 int pick_bucket(const Inst &I, const sng_config *cfg, void *workspace, size_t ws_bytes,
-                size_t used, BucketGeom *B, bool *use)
+                size_t used, BucketGeom *B, bool *use, uint32_t layout = kLayoutPlain)
 {
     *use = false;
     if (I.m == 0 || I.n == 0)
@@ -259,7 +267,7 @@ int pick_bucket(const Inst &I, const sng_config *cfg, void *workspace, size_t ws
     B->start = cv.take<uint32_t>(B->ranges * 2);
     B->queue = cv.take<unsigned long long>(kXcds);
     B->hdr = I.cnt + kSampleHdr;
-    B->tag = sample_tag(I.n, I.m, (uint64_t)I.key0 | ((uint64_t)I.key1 << 32), B->bshift);
+    B->tag = sample_tag(I.n, I.m, (uint64_t)I.key0 | ((uint64_t)I.key1 << 32), B->bshift, layout);
     *use = true;
     return SNG_OK;
 }
@@ -273,7 +281,7 @@ int run_plain(Inst &I, const sng_config *cfg, bool labels_wanted, const BucketGe
         float lo, hi;
         band_fp32(I.eps2, I.d, &lo, &hi, &band);
     }
-    SNG_TRY(init_header(I.cnt, (uint64_t)I.n * I.m, band, st));
+    SNG_TRY(init_header(I.cnt, (uint64_t)I.n * I.m, band, st, true));
     SNG_TRY(launch_fill_u32(I.deg, I.n, 0u, st));
     if (I.m > 0 && B) {
         SNG_TRY(launch_fill_u32(I.mask, I.chunks * 8, 0u, st));
@@ -785,7 +793,7 @@ int sng_dbscan_sweep(const float *X, int64_t n, int32_t d, int64_t ld, double s,
     bool use = false;
     sng_config tuned;
     cfg = effective_cfg(I, cfg, &tuned);
-    if ((rc = pick_bucket(I, cfg, workspace, ws_bytes, cv.off, &B, &use))) return rc;
+    if ((rc = pick_bucket(I, cfg, workspace, ws_bytes, cv.off, &B, &use, kLayoutSweep))) return rc;
     SNG_TRY(init_header(I.cnt, (uint64_t)n * (uint64_t)m, band, st));
     SNG_TRY(launch_fill_u32(S.hist, (uint64_t)n * n_eps, 0u, st));
     SNG_TRY(launch_sweep(I, S, shape_for(I, cfg, use), use ? &B : nullptr, st));

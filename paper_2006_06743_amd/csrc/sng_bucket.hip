@@ -378,6 +378,11 @@ __device__ __forceinline__ void eval_ticket(const Inst &I, const BucketGeom &B, 
             const uint32_t co = v[k] >> kRecOffShift;
             cj[k] = jbase | (v[k] & 0xFFFFu);
             ii[k] = i0 + div_magic(c0 + co, B.cdiv);
+            if (live[k] && !(ii[k] < I.n && cj[k] < I.n)) {  // never for a valid sample
+                live[k] = false;
+                if (q == 0)
+                    atomicAdd(I.cnt + kCntOverflow, 1ull);
+            }
             const uint32_t sj = live[k] ? cj[k] : 0u;  // row 0 always exists
             const uint32_t si = live[k] ? ii[k] : 0u;
             if constexpr (kBuf) {
@@ -534,11 +539,12 @@ size_t bucket_bytes(const BucketGeom &g)
            (size_t)g.ranges * 8 + kXcds * 8 + 1280;
 }
 
-uint64_t sample_tag(int64_t n, int64_t m, uint64_t seed, uint32_t bshift)
+uint64_t sample_tag(int64_t n, int64_t m, uint64_t seed, uint32_t bshift, uint32_t layout)
 {
-    // splitmix64 finaliser over the arguments that fix the records
+    // splitmix64 finaliser over the arguments that fix the records and where
+    // they sit
     uint64_t h = 0x9E3779B97F4A7C15ull;
-    const uint64_t parts[4] = {(uint64_t)n, (uint64_t)m, seed, (uint64_t)bshift};
+    const uint64_t parts[5] = {(uint64_t)n, (uint64_t)m, seed, (uint64_t)bshift, (uint64_t)layout};
     for (uint64_t v : parts) {
         h ^= v + 0x9E3779B97F4A7C15ull + (h << 6) + (h >> 2);
         h ^= h >> 30;

@@ -95,7 +95,11 @@ struct BucketGeom {
 };
 // u64 index of BucketGeom::hdr inside an instance's counter header
 constexpr int kSampleHdr = 32;
-uint64_t sample_tag(int64_t n, int64_t m, uint64_t seed, uint32_t bshift);
+// Workspace layouts whose record areas differ: a sample is valid only for
+// the layout that drew it.
+constexpr uint32_t kLayoutPlain = 1;
+constexpr uint32_t kLayoutSweep = 2;
+uint64_t sample_tag(int64_t n, int64_t m, uint64_t seed, uint32_t bshift, uint32_t layout);
 bool bucket_geometry(int64_t n, int d, int64_t m, bool force, BucketGeom *g);
 size_t bucket_bytes(const BucketGeom &g);
 // Draws and sorts the sample into B (B.hdr gets its tag once complete).

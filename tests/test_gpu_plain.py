@@ -294,9 +294,9 @@ def test_sample_reused_across_eps_and_inputs(sng, orc):
 
 
 def test_stale_sample_is_reported(sng, orc):
-    """A reuse call whose sample is missing (fresh workspace) or was drawn
-    with another seed does no work and is reported through the overflow
-    counter."""
+    """A reuse call whose sample is missing (fresh workspace), was drawn with
+    another seed, or was overwritten by a call with another workspace layout
+    does no work and is reported through the overflow counter."""
     import torch
     rng = np.random.default_rng(516)
     n, d, m = 5000, 3, 40
@@ -315,6 +315,17 @@ def test_stale_sample_is_reported(sng, orc):
     torch.cuda.synchronize()
     st = sng.stats(ws)
     assert st.overflow == 0 and st.accepted > 0
+    # a call with another workspace layout (a sweep, drawing its own sample
+    # into its own record area) invalidates the stored one
+    s = m / n
+    assert sng.samples_per_point(s, n) == m
+    big = torch.zeros(max(ws.numel(), 4 * sng.workspace_size(n, d, m)) + (64 << 20),
+                      dtype=torch.uint8, device="cuda")
+    sng.sample(n, d, m, 8, big)
+    sng.sweep(Xg, s, [0.02, 0.05], [2, 3], 8, ws=big, cfg=sng.Config(schedule=2))
+    deg, _ = sng.degrees(Xg, m, 0.05, 8, cfg=reuse, ws=big)
+    torch.cuda.synchronize()
+    assert sng.stats(big).overflow >= 1
 
 
 @pytest.mark.parametrize("n,d,s", [(40000, 16, 0.002), (60000, 3, 0.002)])
