@@ -11,7 +11,8 @@
  *
  * What this library computes, exactly (the readings that make the output
  * unique; Algorithm 1 leaves these open):
- *   m        = ceil(fl64(s * n)) samples per point (1 <= ... any m >= 0).
+ *   m        = ceil(fl64(s * n)) samples per point (calls that take m
+ *            directly accept any 0 <= m <= 2^31).
  *   sample t of point i (t < m) is j = W[t mod 4] mod n, where
  *            W = Philox4x32-10(counter = (t/4, i, 0, 0),
  *                              key = (seed mod 2^32, seed / 2^32))
@@ -40,10 +41,13 @@
  *     Calls enqueue work on it and return without waiting; outputs are valid
  *     once the stream has been synchronised.
  *   - Arguments are validated before anything is enqueued; a call that
- *     returns an error has written nothing.
+ *     returns a validation error has written nothing. SNG_EHIP reports a HIP
+ *     call or launch that failed after earlier work was enqueued.
  *   - `workspace` is device memory of at least the size reported by the
- *     matching *_workspace_size call; its contents on entry are ignored.
- *     One workspace must not be used by two calls in flight at once.
+ *     matching *_workspace_size call; its contents on entry are ignored,
+ *     except where a call is asked to continue from an earlier one
+ *     (sng_cluster, reuse_sample). One workspace must not be used by two
+ *     calls in flight at once.
  *   - Degrees are 32-bit and wrap beyond 2^32-1 (unreachable in practice:
  *     the expected degree is about 2m).
  */
@@ -113,8 +117,8 @@ typedef struct {
     uint64_t n_core;
     uint64_t n_clusters;
     uint64_t n_noise;
-    uint64_t overflow;   /* non-zero: a recheck queue overflowed, or a reused sample was
-                            missing (results invalid) */
+    uint64_t overflow;   /* non-zero: results invalid (a recheck queue overflowed, or a
+                            reused partner-block sample was missing or damaged) */
     double band_rel;     /* relative half-width of the recheck band used */
 } sng_stats;
 
@@ -125,7 +129,8 @@ const char *sng_status_string(int status);
  * >= 0, n >= 0. Host call, no device work. */
 int sng_samples_per_point(double s, int64_t n, int64_t *m);
 
-/* Bytes of workspace for sng_dbscan / sng_degrees / sng_cluster with n points
+/* Bytes of workspace for sng_dbscan / sng_degrees / sng_cluster / sng_sample /
+ * sng_autotune with n points
  * of dimension d and m samples per point, at precision `prec` (optionally
  * or-ed with SNG_WS_DIRECT). The partner-block schedule keeps 4 bytes per
  * sample slot of records in the workspace. Host call. */
@@ -133,7 +138,8 @@ int sng_workspace_size(int64_t n, int32_t d, int64_t m, int32_t prec, size_t *by
 
 /* Sampling step only (Algorithm 1, graph construction; edges are not stored):
  * degrees[n] (device, u32) receives the symmetrised degree of every point.
- * X: device float32 [n, ld]. cfg may be NULL. */
+ * X: device float32 [n, ld]. cfg may be NULL (the tuned configuration of
+ * this shape if sng_autotune stored one, else the library's defaults). */
 int sng_degrees(const float *X, int64_t n, int32_t d, int64_t ld, int64_t m, double eps,
                 uint64_t seed, uint32_t *degrees, void *workspace, size_t ws_bytes,
                 const sng_config *cfg, void *stream);
