@@ -10,7 +10,7 @@ kernel, the oracle's CPU rate on a bounded sample, and the plain-vs-mixed,
 plain-vs-sweep and sequential-vs-batched comparisons.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--schedule auto|direct]
-                    [--forms mixed,sweep,batch | --no-forms] [--no-cpu-baseline]
+                    [--forms mixed,sweep,batch,recovery | --no-forms] [--no-cpu-baseline]
                     [--calibrate-copy]
 """
 import argparse
@@ -202,8 +202,31 @@ def form_batch(sng, torch, wl, reps):
     return entry
 
 
+def form_recovery(sng, torch, wl, reps):
+    """The paper's simulated recovery study (three uniform balls in R^3,
+    ceil(20 ln n) samples per point): ARI and AMI against the true balls as n
+    grows, with the GPU time of each run."""
+    from sklearn.metrics import adjusted_mutual_info_score, adjusted_rand_score
+    rows = []
+    for n in (1000, 10000, 100000, 1000000):
+        W, truth = wl.balls_3d(n)
+        X = torch.from_numpy(W.X).cuda()
+        lab, deg, ws = sng.dbscan(X, W.s, W.eps, W.min_pts, W.seed)
+        t = _cuda_ms(torch, lambda: sng.dbscan(X, W.s, W.eps, W.min_pts, W.seed, labels=lab,
+                                               degrees_out=deg, ws=ws), reps)
+        got = lab.cpu().numpy()
+        rows.append({"n": n, "m": W.meta["m"], "ms": t,
+                     "ari": float(adjusted_rand_score(truth, got)),
+                     "ami": float(adjusted_mutual_info_score(truth, got)),
+                     "clusters": int(sng.stats(ws).n_clusters),
+                     "noise_fraction": float((got < 0).mean())})
+        del X, ws
+    return {"workload": "balls3d (eps 0.3, MinPts 3, s = ceil(20 ln n) / n)", "runs": rows}
+
+
 FORMS = {"mixed": ("mixed_precision", form_mixed), "sweep": ("sweep", form_sweep),
-         "batch": ("batch", form_batch)}
+         "batch": ("batch", form_batch),
+         "recovery": ("recovery", form_recovery)}
 
 
 def time_forms(sng, torch, wl, which, reps=3):
@@ -226,8 +249,8 @@ def main():
     ap.add_argument("--schedule", choices=["tuned", "auto", "direct"], default="tuned",
                     help="tuned: the autotuner's choice (timed before the run); auto: the "
                          "library's rule (partner blocks here); direct: direct gathers")
-    ap.add_argument("--forms", default="mixed,sweep,batch",
-                    help="comma-separated subset of mixed, sweep, batch")
+    ap.add_argument("--forms", default="mixed,sweep,batch,recovery",
+                    help="comma-separated subset of mixed, sweep, batch, recovery")
     ap.add_argument("--no-forms", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",

@@ -226,6 +226,26 @@ def lidar_3d(data_seed: int = 1005, n_total: int = 5_000_000) -> Workload:
                     min_pts=4, seed=5, meta={"data_seed": data_seed})
 
 
+def balls_3d(n: int, data_seed: int = 1061) -> tuple[Workload, np.ndarray]:
+    """Three uniform balls in R^3 (the paper's simulated recovery study,
+    Section 3, Fig. 1): equal weights, radius 1, centres on an equilateral
+    triangle of side 4; ceil(20 ln n) samples per point (s = that / n),
+    eps = 0.3, MinPts = 3, sampler seed 6. Returns the workload and the
+    true ball of every point (after the shuffle)."""
+    rng = np.random.default_rng(data_seed)
+    centres = np.array([[0.0, 0.0, 0.0], [4.0, 0.0, 0.0], [2.0, 2.0 * math.sqrt(3.0), 0.0]])
+    ball = rng.integers(0, 3, n)
+    u = rng.normal(size=(n, 3))
+    u /= np.linalg.norm(u, axis=1, keepdims=True)
+    r = rng.random(n) ** (1.0 / 3.0)
+    X = centres[ball] + u * r[:, None]
+    perm = rng.permutation(n)
+    m = int(math.ceil(20.0 * math.log(n))) if n > 1 else 1
+    W = Workload("balls3d_n%d" % n, np.ascontiguousarray(X[perm].astype(np.float32)),
+                 s=m / n, eps=0.3, min_pts=3, seed=6, meta={"data_seed": data_seed, "m": m})
+    return W, ball[perm]
+
+
 def random_instance(rng: np.random.Generator, n: int, d: int, kind: str = "blobs",
                     spread: float = 0.05) -> np.ndarray:
     """Small random point sets for property and parity tests.

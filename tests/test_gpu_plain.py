@@ -387,3 +387,22 @@ def test_graph_deep_forests(sng):
         got = labels.cpu().numpy()
         bad = np.nonzero(got != want)[0]
         assert bad.size == 0, "%d labels differ (first %s)" % (bad.size, bad[:5])
+
+
+def test_balls_recovery(sng, orc):
+    """The simulated recovery study (three uniform balls, ceil(20 ln n)
+    samples per point): labels equal the oracle's at n = 1e4, and recovery
+    of the true balls improves with n. The improvement is the paper's
+    qualitative claim (Theorem 1, Fig. 1), not a parity pin."""
+    from sklearn.metrics import adjusted_rand_score
+    W, truth = wl.balls_3d(10000)
+    gl, gd, st = run(sng, W.X, W.s, W.eps, W.min_pts, W.seed)
+    ref = orc.dbscan(W.X, W.eps, W.min_pts, W.seed, s=W.s)
+    assert_same(gl, gd, ref, W.name)
+    scores = []
+    for n in (1000, 10000, 100000):
+        W, truth = wl.balls_3d(n)
+        print("recovery n", n, flush=True)
+        gl, gd, st = run(sng, W.X, W.s, W.eps, W.min_pts, W.seed)
+        scores.append(adjusted_rand_score(truth, gl))
+    assert scores[0] < scores[1] < scores[2] and scores[2] > 0.8, scores

@@ -41,3 +41,22 @@ def test_mnistlike_eps_rederived(orc):
     mod = importlib.util.module_from_spec(spec)
     spec.loader.exec_module(mod)
     assert float(mod.derive()["eps"]) == w.MNISTLIKE_EPS
+
+
+def test_balls_3d_geometry():
+    """Three unit balls, equal weights, ceil(20 ln n) samples per point."""
+    import math
+    W, truth = w.balls_3d(30000)
+    assert W.X.shape == (30000, 3) and W.X.dtype == np.float32
+    assert W.meta["m"] == math.ceil(20 * math.log(30000))
+    assert math.ceil(W.s * W.n) == W.meta["m"]
+    centres = np.array([[0.0, 0.0, 0.0], [4.0, 0.0, 0.0], [2.0, 2.0 * math.sqrt(3.0), 0.0]])
+    r = np.linalg.norm(W.X.astype(np.float64) - centres[truth], axis=1)
+    assert r.max() <= 1.0 + 1e-6
+    # uniform in the ball: P(r <= 1/2) = 1/8
+    assert abs((r <= 0.5).mean() - 0.125) < 0.01
+    counts = np.bincount(truth, minlength=3)
+    assert np.all(np.abs(counts / 30000 - 1 / 3) < 0.02)
+    # balls are more than 2 eps apart
+    gaps = [np.linalg.norm(centres[a] - centres[b]) - 2 for a in range(3) for b in range(a)]
+    assert min(gaps) > 2 * W.eps
