@@ -10,7 +10,8 @@ kernel, the oracle's CPU rate on a bounded sample, and the plain-vs-mixed,
 plain-vs-sweep and sequential-vs-batched comparisons.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--schedule auto|direct]
-                    [--forms mixed,sweep,batch,recovery | --no-forms] [--no-cpu-baseline]
+                    [--forms small,mixed,sweep,batch,lidar,recovery | --no-forms]
+                    [--no-cpu-baseline]
                     [--calibrate-copy]
 """
 import argparse
@@ -224,9 +225,59 @@ def form_recovery(sng, torch, wl, reps):
     return {"workload": "balls3d (eps 0.3, MinPts 3, s = ceil(20 ln n) / n)", "runs": rows}
 
 
+def form_small(sng, torch, wl, reps):
+    """The 10,000 x 2 workload (1e6 slots), bound by launch latency: the
+    whole call in microseconds against a floor of as many empty launches."""
+    W = wl.blobs_2d()
+    X = torch.from_numpy(W.X).cuda()
+    lab, deg, ws = sng.dbscan(X, W.s, W.eps, W.min_pts, W.seed)
+    r = max(reps, 50)
+    t_call = _cuda_ms(torch, lambda: sng.dbscan(X, W.s, W.eps, W.min_pts, W.seed, labels=lab,
+                                                degrees_out=deg, ws=ws), r)
+    # the call enqueues this many kernels (rocprofv3 kernel trace of one call)
+    launches = 7
+    tiny = torch.zeros(1, device="cuda")
+
+    def empty():
+        for _ in range(launches):
+            tiny.add_(0.0)
+    t_floor = _cuda_ms(torch, empty, r)
+    return {"workload": W.name, "slots": W.n * sng.samples_per_point(W.s, W.n),
+            "call_us": t_call * 1e3, "launches": launches,
+            "empty_launches_us": t_floor * 1e3, "over_floor": t_call / t_floor}
+
+
+def form_lidar(sng, torch, wl, reps):
+    """The 5e6-point LiDAR scene (1.25e10 slots): the partner-block pass
+    (sample + evaluate) against direct gathers, and the whole method."""
+    W = wl.lidar_3d()
+    X = torch.from_numpy(W.X).cuda()
+    m = sng.samples_per_point(W.s, W.n)
+    slots = W.n * m
+    ws = torch.empty(sng.workspace_size(W.n, W.d, m), dtype=torch.uint8, device="cuda")
+    sng.sample(W.n, W.d, m, W.seed, ws)
+    deg, _ = sng.degrees(X, m, W.eps, W.seed, cfg=sng.Config(reuse_sample=1), ws=ws)
+    reps = max(1, min(reps, 2))
+    t_sample = _cuda_ms(torch, lambda: sng.sample(W.n, W.d, m, W.seed, ws), reps)
+    t_eval = _cuda_ms(torch, lambda: sng.degrees(X, m, W.eps, W.seed, out=deg, ws=ws,
+                                                 cfg=sng.Config(reuse_sample=1)), reps)
+    t_direct = _cuda_ms(torch, lambda: sng.degrees(X, m, W.eps, W.seed, out=deg, ws=ws,
+                                                   cfg=sng.Config(schedule=1)), reps)
+    lab, deg2, ws2 = sng.dbscan(X, W.s, W.eps, W.min_pts, W.seed, ws=ws)
+    t_all = _cuda_ms(torch, lambda: sng.dbscan(X, W.s, W.eps, W.min_pts, W.seed, labels=lab,
+                                               degrees_out=deg2, ws=ws), reps)
+    alg = slots * W.d * 4
+    return {"workload": W.name, "slots": slots, "sample_ms": t_sample, "evaluate_ms": t_eval,
+            "pass_ms": t_sample + t_eval, "direct_pass_ms": t_direct,
+            "speedup_vs_direct": t_direct / (t_sample + t_eval), "dbscan_ms": t_all,
+            "pair_evals_per_s": slots / ((t_sample + t_eval) * 1e-3),
+            "alg_gbs": alg / ((t_sample + t_eval) * 1e-3) / 1e9}
+
+
 FORMS = {"mixed": ("mixed_precision", form_mixed), "sweep": ("sweep", form_sweep),
          "batch": ("batch", form_batch),
-         "recovery": ("recovery", form_recovery)}
+         "recovery": ("recovery", form_recovery), "small": ("small", form_small),
+         "lidar": ("lidar", form_lidar)}
 
 
 def time_forms(sng, torch, wl, which, reps=3):
@@ -249,8 +300,9 @@ def main():
     ap.add_argument("--schedule", choices=["tuned", "auto", "direct"], default="tuned",
                     help="tuned: the autotuner's choice (timed before the run); auto: the "
                          "library's rule (partner blocks here); direct: direct gathers")
-    ap.add_argument("--forms", default="mixed,sweep,batch,recovery",
-                    help="comma-separated subset of mixed, sweep, batch, recovery")
+    ap.add_argument("--forms", default="small,mixed,sweep,batch,lidar,recovery",
+                    help="comma-separated subset of small, mixed, sweep, batch, lidar, "
+                         "recovery")
     ap.add_argument("--no-forms", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
