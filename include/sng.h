@@ -86,6 +86,7 @@ typedef struct {
     int32_t prefetch;        /* partner rows a group gathers ahead: 4, 8 or 16 */
     int32_t schedule;        /* 0 auto, 1 direct gathers, 2 partner-block (L2 reuse) */
     int32_t reuse_sample;    /* 1: evaluate the sample sng_sample left in the workspace */
+    int32_t out_degree;      /* 1: degree = a point's own accepted samples (see below) */
 } sng_config;
 /* schedule: the partner-block form sorts the sample slots by partner block
  * before gathering, so rows narrower than a 128-byte line are reused from
@@ -103,6 +104,14 @@ typedef struct {
  * layouts clear it); a missing or different sample does no work and makes
  * sng_stats_read report SNG_EOVERFLOW, and every decoded index is range
  * checked as well. */
+
+/* out_degree (sng_degrees, sng_dbscan, sng_dbscan_lowp, sng_dbscan_sweep):
+ * the degree of a point, and so its core test, counts only its own accepted
+ * samples (the neighbour count analysed in Lemma 2 of Section 4.1) instead
+ * of the symmetrised count; the graph, and so components and borders, is
+ * unchanged. The other fields choose a launch shape and never change a
+ * result. A config whose launch-shape fields are all zero still runs with
+ * the tuned shape of sng_autotune. */
 
 /* Flag for sng_workspace_size: size for the direct schedule only (smaller;
  * a workspace of that size makes the automatic schedule choose it). */

@@ -144,9 +144,12 @@ def slot_sqdist(X: np.ndarray, m: int, seed: int, i0: int = 0, i1: Optional[int]
 
 
 def dbscan(X: np.ndarray, eps: float, min_pts: int, seed: int = 0, s: Optional[float] = None,
-           m: Optional[int] = None, exhaustive: bool = False) -> Result:
+           m: Optional[int] = None, exhaustive: bool = False,
+           out_degree: bool = False) -> Result:
     """SNG-DBSCAN (Algorithm 1). Give ``s`` (m = ceil(s*n)) or ``m``;
-    ``exhaustive=True`` uses the full eps-neighbourhood graph instead."""
+    ``exhaustive=True`` uses the full eps-neighbourhood graph instead;
+    ``out_degree=True`` counts only a point's own accepted samples in its
+    degree (Lemma 2, Section 4.1)."""
     X = _rows(X)
     n, d = X.shape
     if not exhaustive:
@@ -158,7 +161,8 @@ def dbscan(X: np.ndarray, eps: float, min_pts: int, seed: int = 0, s: Optional[f
     deg = np.zeros(n, np.uint32)
     st = np.zeros(8, np.uint64)
     _check(load().sng_oracle_dbscan(_ptr(X), n, d, d, int(m or 0), float(eps), int(min_pts),
-                                    int(seed), 1 if exhaustive else 0, _ptr(labels), _ptr(deg),
+                                    int(seed), 1 if exhaustive else (2 if out_degree else 0),
+                                    _ptr(labels), _ptr(deg),
                                     _ptr(st)), "sng_oracle_dbscan")
     return _result(labels, deg, st)
 

@@ -178,7 +178,7 @@ static int valid_eps(double eps)
  * pairs gathered into *out (order irrelevant to everything downstream). */
 static int sample_graph(const float *X, int64_t n, int32_t d, int64_t ld, int64_t m, double eps,
                         uint64_t seed, int64_t i0, int64_t i1, uint32_t *deg, uint64_t *stats,
-                        pairlist *out)
+                        pairlist *out, int symmetrised)
 {
     const double eps2 = eps * eps;
     int nthreads = 1;
@@ -207,8 +207,10 @@ static int sample_graph(const float *X, int64_t n, int32_t d, int64_t ld, int64_
                     acc_total++;
 #pragma omp atomic
                     deg[i]++;
+                    if (symmetrised) {
 #pragma omp atomic
-                    deg[j]++;
+                        deg[j]++;
+                    }
                     if (out)
                         pl_push(&lists[tid], i, j);
                 }
@@ -256,7 +258,7 @@ int sng_oracle_degrees_range(const float *X, int64_t n, int32_t d, int64_t ld, i
         return -1;
     if (n == 0)
         return 0;
-    return sample_graph(X, n, d, ld, m, eps, seed, i0, i1, deg, stats, NULL);
+    return sample_graph(X, n, d, ld, m, eps, seed, i0, i1, deg, stats, NULL, 1);
 }
 
 int sng_oracle_slot_sqdist(const float *X, int64_t n, int32_t d, int64_t ld, int64_t m,
@@ -367,10 +369,10 @@ int sng_oracle_dbscan(const float *X, int64_t n, int32_t d, int64_t ld, int64_t 
                       double eps, int32_t min_pts, uint64_t seed, int32_t mode,
                       int32_t *labels, uint32_t *deg, uint64_t *stats)
 {
-    if (!valid_points(X, n, d, ld) || !valid_eps(eps) || (mode != 0 && mode != 1) ||
-        (n > 0 && !labels) || (mode == 0 && m < 0))
+    if (!valid_points(X, n, d, ld) || !valid_eps(eps) || mode < 0 || mode > 2 ||
+        (n > 0 && !labels) || (mode != 1 && m < 0))
         return -1;
-    if (mode == 0 && (m > 17179869184LL || (m > 0 && n > INT64_MAX / m)))
+    if (mode != 1 && (m > 17179869184LL || (m > 0 && n > INT64_MAX / m)))
         return -2;
     uint64_t local[8] = {0};
     uint32_t *dg = deg ? deg : (uint32_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(uint32_t));
@@ -379,9 +381,11 @@ int sng_oracle_dbscan(const float *X, int64_t n, int32_t d, int64_t ld, int64_t 
     memset(dg, 0, (size_t)n * sizeof(uint32_t));
     pairlist A = {0};
     int rc = 0;
-    if (mode == 0) {
+    if (mode != 1) {
+        /* mode 2: a point's degree counts only its own accepted samples (the
+         * neighbour count of Lemma 2's proof); the graph is the same */
         if (n > 0)
-            rc = sample_graph(X, n, d, ld, m, eps, seed, 0, n, dg, local, &A);
+            rc = sample_graph(X, n, d, ld, m, eps, seed, 0, n, dg, local, &A, mode == 0);
     } else {
         /* exhaustive: the full eps-neighbourhood graph of classical DBSCAN */
         const double eps2 = eps * eps;

@@ -67,7 +67,10 @@ int sng_oracle_slot_sqdist(const float *X, int64_t n, int32_t d, int64_t ld, int
 
 /* Whole method. mode 0: Philox-sampled graph with m samples per point.
  * mode 1: exhaustive graph (every unordered pair i<j once; m ignored), i.e.
- * full DBSCAN on the same post-processing. labels[n] and deg[n] are written;
+ * full DBSCAN on the same post-processing. mode 2: the sampled graph of mode
+ * 0, but a point's degree (and so its core test) counts only its own
+ * accepted samples (Lemma 2, Section 4.1, and its proof); components and
+ * borders still use every accepted pair. labels[n] and deg[n] are written;
  * deg may be NULL. */
 int sng_oracle_dbscan(const float *X, int64_t n, int32_t d, int64_t ld, int64_t m,
                       double eps, int32_t min_pts, uint64_t seed, int32_t mode,

@@ -37,11 +37,12 @@ class Config:
     prefetch: int = 0
     schedule: int = 0  # 0 auto, 1 direct gathers, 2 partner-block (L2 reuse)
     reuse_sample: int = 0  # 1: evaluate the sample that sample() left in the workspace
+    out_degree: int = 0    # 1: a point's degree counts only its own accepted samples
 
     def c(self):
         return ctypes.byref(sng_config(self.lanes_per_pair, self.chunks_per_wave,
                                        self.stage_lds, self.prefetch, self.schedule,
-                                       self.reuse_sample))
+                                       self.reuse_sample, self.out_degree))
 
 
 @dataclass
@@ -129,7 +130,7 @@ def sample(n: int, d: int, m: int, seed: int, ws: torch.Tensor):
 
 def _config_of(c) -> Config:
     return Config(c.lanes_per_pair, c.chunks_per_wave, c.stage_lds, c.prefetch, c.schedule,
-                  c.reuse_sample)
+                  c.reuse_sample, c.out_degree)
 
 
 def autotune(X: torch.Tensor, m: int, eps: float, seed: int, trials: int = 2,

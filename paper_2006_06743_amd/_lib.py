@@ -30,7 +30,8 @@ EXPORTS = [
 class sng_config(ctypes.Structure):
     _fields_ = [("lanes_per_pair", ctypes.c_int32), ("chunks_per_wave", ctypes.c_int32),
                 ("stage_lds", ctypes.c_int32), ("prefetch", ctypes.c_int32),
-                ("schedule", ctypes.c_int32), ("reuse_sample", ctypes.c_int32)]
+                ("schedule", ctypes.c_int32), ("reuse_sample", ctypes.c_int32),
+                ("out_degree", ctypes.c_int32)]
 
 
 class sng_stats(ctypes.Structure):

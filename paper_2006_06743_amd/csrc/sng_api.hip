@@ -163,6 +163,8 @@ int check_cfg(const sng_config *cfg)
         return SNG_EINVAL;
     if (cfg->reuse_sample && (cfg->schedule == 1 || cfg->stage_lds))
         return SNG_EINVAL;  // a stored sample is evaluated by the partner-block schedule only
+    if (cfg->out_degree != 0 && cfg->out_degree != 1)
+        return SNG_EINVAL;
     return SNG_OK;
 }
 
@@ -220,6 +222,7 @@ TuneKey tune_key(const float *X, int32_t d, int64_t ld, int64_t n, int64_t m)
     return TuneKey{d, vec, ceil_log2((uint64_t)n), ceil_log2((uint64_t)m)};
 }
 
+// No launch shape chosen by the caller (out_degree is not a launch choice).
 bool is_default_cfg(const sng_config *cfg)
 {
     return !cfg || (cfg->lanes_per_pair == 0 && cfg->chunks_per_wave == 0 && cfg->stage_lds == 0 &&
@@ -241,6 +244,7 @@ const sng_config *effective_cfg(const Inst &I, const sng_config *cfg, sng_config
     *buf = it->second;
     if (buf->schedule == 2)
         buf->schedule = kPreferPartner;
+    buf->out_degree = cfg ? cfg->out_degree : 0;
     return buf;
 }
 
@@ -362,6 +366,7 @@ int sng_degrees(const float *X, int64_t n, int32_t d, int64_t ld, int64_t m, dou
     hipStream_t st = (hipStream_t)stream;
     Carve cv(workspace);
     Inst I = make_inst(X, n, d, ld, m, eps, seed, 0);
+    I.out_deg = (cfg && cfg->out_degree) ? 1 : 0;
     I.cnt = cv.take<unsigned long long>(kHeaderBytes / 8);
     (void)cv.take<uint32_t>((size_t)n);
     I.core = cv.take<uint8_t>((size_t)n);
@@ -578,6 +583,7 @@ int sng_dbscan(const float *X, int64_t n, int32_t d, int64_t ld, double s, doubl
     hipStream_t st = (hipStream_t)stream;
     Carve cv(workspace);
     Inst I = make_inst(X, n, d, ld, m, eps, seed, min_pts);
+    I.out_deg = (cfg && cfg->out_degree) ? 1 : 0;
     I.cnt = cv.take<unsigned long long>(kHeaderBytes / 8);
     uint32_t *wdeg = cv.take<uint32_t>((size_t)n);
     I.core = cv.take<uint8_t>((size_t)n);
@@ -601,6 +607,7 @@ int sng_dbscan_lowp(const float *X, int64_t n, int32_t d, int64_t ld, const uint
         return SNG_EINVAL;  // the mixed form draws its own sample
     int rc = check_points(X, n, d, ld);
     if (rc) return rc;
+    if ((rc = check_cfg(cfg))) return rc;
     if ((rc = check_eps(eps))) return rc;
     if (prec != SNG_BF16 && prec != SNG_FP16) return SNG_EINVAL;
     if (!(lp_scale == lp_scale) || __builtin_isinf(lp_scale) || lp_scale == 0.0f) return SNG_EINVAL;
@@ -615,6 +622,7 @@ int sng_dbscan_lowp(const float *X, int64_t n, int32_t d, int64_t ld, const uint
     hipStream_t st = (hipStream_t)stream;
     Carve cv(workspace);
     Inst I = make_inst(X, n, d, ld, m, eps, seed, min_pts);
+    I.out_deg = (cfg && cfg->out_degree) ? 1 : 0;
     I.cnt = cv.take<unsigned long long>(kHeaderBytes / 8);
     uint32_t *wdeg = cv.take<uint32_t>((size_t)n);
     I.core = cv.take<uint8_t>((size_t)n);
@@ -768,6 +776,7 @@ int sng_dbscan_sweep(const float *X, int64_t n, int32_t d, int64_t ld, double s,
     hipStream_t st = (hipStream_t)stream;
     Carve cv(workspace);
     Inst I = make_inst(X, n, d, ld, m, eps[n_eps - 1], seed, 0);
+    I.out_deg = (cfg && cfg->out_degree) ? 1 : 0;
     I.cnt = cv.take<unsigned long long>(kHeaderBytes / 8);
     SweepArgs S;
     memset(&S, 0, sizeof(S));

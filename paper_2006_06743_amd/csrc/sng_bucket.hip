@@ -33,6 +33,7 @@ constexpr uint32_t kRecOffShift = 18;  // record: call offset (14 bits) | word (
 // formed only inside the band. record() receives the slot's global call
 // number as a functor, evaluated only for accepted slots.
 struct BucketPlainPolicy {
+    int out_deg;  // 1: out-degrees (no partner-side count)
     const float *X;
     int64_t ld;
     int d;
@@ -57,7 +58,8 @@ struct BucketPlainPolicy {
         if (acc && q == 0) {
             const uint64_t call = call_of();
             atomicAdd(deg + i, 1u);
-            atomicAdd(deg + j, 1u);
+            if (!out_deg)
+                atomicAdd(deg + j, 1u);
             atomicOr(mask + (call >> 3), 1u << (4 * (call & 7) + w));
             t.accepted += 1;
         }
@@ -65,6 +67,7 @@ struct BucketPlainPolicy {
 };
 
 struct BucketSweepPolicy {
+    int out_deg;  // 1: out-degrees (no partner-side count)
     const float *X;
     int64_t ld;
     int d;
@@ -104,7 +107,8 @@ struct BucketSweepPolicy {
         if (b < K && q == 0) {
             const uint64_t call = call_of();
             atomicAdd(hist + (uint64_t)i * K + b, 1u);
-            atomicAdd(hist + (uint64_t)j * K + b, 1u);
+            if (!out_deg)
+                atomicAdd(hist + (uint64_t)j * K + b, 1u);
             codes[call * 4ull + (uint64_t)w] = (uint8_t)b;
             t.accepted += 1;
         }
@@ -456,6 +460,7 @@ __global__ __launch_bounds__(256) void k_bkt_eval_plain(Inst I, BucketGeom B)
     if (!sample_ok(I, B))
         return;
     BucketPlainPolicy pol;
+    pol.out_deg = I.out_deg;
     pol.X = I.X;
     pol.ld = I.ld;
     pol.d = I.d;
@@ -483,6 +488,7 @@ __global__ __launch_bounds__(256) void k_bkt_eval_sweep(Inst I, BucketGeom B, Sw
     }
     __syncthreads();
     BucketSweepPolicy pol;
+    pol.out_deg = I.out_deg;
     pol.X = I.X;
     pol.ld = I.ld;
     pol.d = I.d;

@@ -42,13 +42,13 @@ struct Inst {
     uint64_t calls;         // n*C
     uint64_t chunk0;        // first global 64-call chunk of this instance
     uint64_t chunks;        // chunks of this instance
-    uint32_t *deg;          // [n] symmetrised degrees
+    uint32_t *deg;          // [n] degrees (symmetrised, or out-degrees if out_deg)
     uint32_t *mask;         // accept bits, 32 per word = 8 calls; indexed by global call
     uint8_t *core;          // [n]
     int32_t *labels;        // [n] union-find parents / border candidates / labels
     unsigned long long *cnt;  // counters (kCntNum)
     int32_t min_pts;
-    int32_t pad_;
+    int32_t out_deg;        // 1: a point's degree counts only its own accepted samples
     double band;              // relative half-width of the binary32 band (reported)
 };
 

@@ -205,7 +205,8 @@ __global__ __launch_bounds__(256) void k_lowp_pass_a(Inst I, LowpArgs L, int KS)
                     }
                 }
                 if (dec == 1) {
-                    atomicAdd(I.deg + jp, 1u);
+                    if (!I.out_deg)
+                        atomicAdd(I.deg + jp, 1u);
                     acc_acc += 1;
                     const uint64_t g = i * (uint64_t)I.C + (t >> 2);
                     atomicOr(I.mask + (g >> 3), 1u << (4 * (g & 7) + (t & 3)));
@@ -308,7 +309,8 @@ __global__ __launch_bounds__(kWave * kRecheckWaves) void k_lowp_recheck(Inst I, 
         }
         if (live && acc <= I.eps2) {
             atomicAdd(I.deg + i, 1u);
-            atomicAdd(I.deg + j, 1u);
+            if (!I.out_deg)
+                atomicAdd(I.deg + j, 1u);
             const uint64_t g = (uint64_t)i * (uint64_t)I.C + (t >> 2);
             atomicOr(I.mask + (g >> 3), 1u << (4 * (g & 7) + (t & 3)));
             acc_n += 1;

@@ -31,6 +31,7 @@ struct PlainPolicy {
     uint32_t *mask;
     float lo, hi;
     double eps2;
+    int out_deg = 0;     // 1: out-degrees (no partner-side count)
     uint32_t deg_i = 0;  // accepted slots of the cached source row
     uint32_t nib = 0;    // accept bits of this lane's own call
 
@@ -57,7 +58,8 @@ struct PlainPolicy {
         if (acc) {
             deg_i += 1;
             if (q == 0) {
-                atomicAdd(deg + j, 1u);
+                if (!out_deg)
+                    atomicAdd(deg + j, 1u);
                 t.accepted += 1;
             }
             if (q == o)
@@ -82,6 +84,7 @@ __device__ __forceinline__ PlainPolicy plain_policy(const Inst &I)
     p.lo = I.lo;
     p.hi = I.hi;
     p.eps2 = I.eps2;
+    p.out_deg = I.out_deg;
     return p;
 }
 

@@ -22,6 +22,7 @@ namespace sng {
 
 // Level decision of one slot. Thresholds live in LDS.
 struct SweepPolicy {
+    int out_deg = 0;  // 1: out-degrees (no partner-side count)
     uint32_t *hist;   // [n][K]
     uint32_t *codes;  // one word of four level codes per Philox call
     const float *lo;
@@ -60,7 +61,8 @@ struct SweepPolicy {
     {
         if (b < K && q == 0) {
             atomicAdd(hist + (uint64_t)i * K + b, 1u);
-            atomicAdd(hist + (uint64_t)j * K + b, 1u);
+            if (!out_deg)
+                atomicAdd(hist + (uint64_t)j * K + b, 1u);
             t.accepted += 1;
         }
         if (q == o)
@@ -93,6 +95,7 @@ __global__ __launch_bounds__(256) void k_sweep_pass(Inst I, SweepArgs S, uint32_
     pol.e2 = s_e2;
     pol.K = S.K;
     pol.hi_max = S.c.hi[S.K - 1];
+    pol.out_deg = I.out_deg;
     const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
     const uint64_t lo = wave * cpw;
     float *slice = lds + (threadIdx.x / kWave) * slice_floats;

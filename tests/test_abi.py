@@ -110,7 +110,7 @@ def test_invalid_arguments_rejected_before_launch(lib):
     assert lib.sng_sample(10, 2, 2**31 + 1, 1, ws, 10**9, None) == -2
     assert lib.sng_sample(10, 2, 10, 1, ws, 10, None) == -3
     assert lib.sng_sample(10, 2, 10, 1, None, 10**9, None) == -3
-    for fields in [(0, 0, 0, 0, 0, 2), (0, 0, 0, 0, 1, 1), (0, 0, 1, 0, 0, 1)]:
+    for fields in [(0, 0, 0, 0, 0, 2), (0, 0, 0, 0, 1, 1), (0, 0, 1, 0, 0, 1), (0, 0, 0, 0, 0, 0, 2)]:
         c = sng_config(*fields)
         assert lib.sng_dbscan(fake, 10, 2, 2, 0.5, 1.0, 3, 1, lab, None, ws, 10**9,
                               ctypes.byref(c), None) == -1, fields

@@ -144,3 +144,21 @@ def test_batch_64_uneven_full(sng, orc):
     labels, degs = plan.launch()
     torch.cuda.synchronize()
     check_batch(orc, B, labels, degs, "graph")
+
+
+@pytest.mark.parametrize("schedule", [1, 2], ids=["direct", "partner_blocks"])
+def test_sweep_out_degree(sng, orc, schedule):
+    """The sweep with out-degrees equals single out-degree runs."""
+    import torch
+    rng = np.random.default_rng(4321)
+    X = wl.random_instance(rng, 3000, 4, "blobs", spread=0.03)
+    eps, mps, s, seed = [0.01, 0.03, 0.08], [1, 2, 4], 0.02, 99
+    labels, degs, ws = sng.sweep(gpu(X), s, eps, mps, seed,
+                                 cfg=sng.Config(schedule=schedule, out_degree=1))
+    torch.cuda.synchronize()
+    L = labels.cpu().numpy()
+    D = degs.cpu().numpy().view(np.uint32)
+    for ki, e in enumerate(eps):
+        for pi, mp in enumerate(mps):
+            ref = orc.dbscan(X, e, mp, seed, s=s, out_degree=True)
+            assert_same(L[pi, ki], D[ki], ref, "eps=%g MinPts=%d" % (e, mp))

@@ -150,3 +150,18 @@ def test_bad_copy_still_exact(sng, orc):
     ref = orc.dbscan(X, 0.06, 3, 2, s=0.2)
     gl, gd, st = run_lowp(sng, X, bits, 0.2, 0.06, 3, 2, 1)
     assert_same(gl, gd, ref, "bad copy")
+
+
+@pytest.mark.parametrize("prec", [1, 2], ids=["bf16", "fp16"])
+def test_out_degree_mode_lowp(sng, orc, prec):
+    """The mixed form with out-degrees equals the oracle's out-degree mode."""
+    import torch
+    rng = np.random.default_rng(77 + prec)
+    X = wl.random_instance(rng, 3000, 48, "blobs", spread=0.05)
+    seed = 31
+    Xg = torch.from_numpy(np.ascontiguousarray(X)).cuda()
+    lab, deg, ws = sng.dbscan_lowp(Xg, lp_tensor(bits_for(X, prec)), 0.05, 0.4, 3, seed,
+                                   prec=prec, cfg=sng.Config(out_degree=1))
+    torch.cuda.synchronize()
+    ref = orc.dbscan(X, 0.4, 3, seed, s=0.05, out_degree=True)
+    assert_same(lab.cpu().numpy(), deg.cpu().numpy().view(np.uint32), ref, "lowp out-degree")

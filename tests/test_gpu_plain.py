@@ -406,3 +406,24 @@ def test_balls_recovery(sng, orc):
         gl, gd, st = run(sng, W.X, W.s, W.eps, W.min_pts, W.seed)
         scores.append(adjusted_rand_score(truth, gl))
     assert scores[0] < scores[1] < scores[2] and scores[2] > 0.8, scores
+
+
+@pytest.mark.parametrize("schedule", [1, 2], ids=["direct", "partner_blocks"])
+def test_out_degree_mode(sng, orc, schedule):
+    """out_degree = 1: degrees count only a point's own accepted samples
+    (Lemma 2); labels follow from those core sets. Oracle mode out_degree."""
+    rng = np.random.default_rng(2024 + schedule)
+    for case in range(6):
+        n = int(rng.integers(500, 20000))
+        d = int(rng.choice([2, 3, 5, 16]))
+        X = wl.random_instance(rng, n, d, "blobs", spread=0.03)
+        s = float(rng.choice([0.01, 0.05]))
+        eps = float(rng.choice([0.02, 0.05]))
+        mp = int(rng.choice([1, 2, 4]))
+        seed = int(rng.integers(0, 2**63))
+        print("out-degree case", case, n, d, s, eps, mp, flush=True)
+        gl, gd, st = run(sng, X, s, eps, mp, seed,
+                         cfg=sng.Config(schedule=schedule, out_degree=1))
+        ref = orc.dbscan(X, eps, mp, seed, s=s, out_degree=True)
+        assert_same(gl, gd, ref, "out-degree case %d" % case)
+        assert st.accepted == ref.accepted and int(gd.sum()) == ref.accepted

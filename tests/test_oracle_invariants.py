@@ -116,3 +116,30 @@ def test_thread_count_does_not_change_result(orc, tmp_path):
                        env=dict(os.environ, OMP_NUM_THREADS=th))
         outs.append(np.load(f))
     assert np.array_equal(outs[0], outs[1])
+
+
+def test_out_degree_mode(orc):
+    """Out-degree mode (Lemma 2): a point's degree is the number of its own
+    accepted samples. With eps covering everything it is m minus its self
+    samples; in general out + in = the symmetrised degree, the out-degrees
+    sum to the accepted count, and the graph (so the components among equal
+    core sets) is unchanged."""
+    rng = np.random.default_rng(5150)
+    X = random_instance(rng, 700, 3, "blobs", spread=0.05)
+    m = 30
+    big = orc.dbscan(X, 1e6, 1, 9, m=m, out_degree=True)
+    selfs = np.array([sum(orc.partner(9, 700, i, t) == i for t in range(m)) for i in range(700)])
+    assert np.array_equal(big.deg, (m - selfs).astype(np.uint32))
+    for eps in (0.02, 0.05, 0.2):
+        o = orc.dbscan(X, eps, 2, 9, m=m, out_degree=True)
+        s = orc.dbscan(X, eps, 2, 9, m=m)
+        assert int(o.deg.sum()) == o.accepted == s.accepted
+        # out-degree recounted slot by slot from the binary64 distances
+        D = orc.slot_sqdist(X, m, 9)
+        own = ((D >= 0) & (D <= eps * eps)).sum(axis=1)
+        assert np.array_equal(o.deg, own.astype(np.uint32))
+        assert np.all(o.deg <= s.deg)
+        # MinPts <= 0: every point core in both modes, so labels coincide
+        o0 = orc.dbscan(X, eps, 0, 9, m=m, out_degree=True)
+        s0 = orc.dbscan(X, eps, 0, 9, m=m)
+        assert np.array_equal(o0.labels, s0.labels)
