@@ -321,16 +321,38 @@ __device__ __forceinline__ void st_relaxed(int32_t *p, int32_t v)
 
 // Root of x, halving the path on the way (any written value is an ancestor,
 // so concurrent finds and hooks stay consistent).
+//
+// The walk reads and writes the forest through the compute unit's own
+// caches (workgroup-scope relaxed accesses), so it may see parent pointers
+// that other XCDs have since lowered. That is safe for three reasons: a
+// parent always has a smaller index than its child, so any walk ends; every
+// pointer ever stored joins two points of one component, so a stale root
+// still names the right component, and a stale halving store still writes an
+// ancestor; and the compare-and-swap that hooks a root acts at device scope
+// on the current value, so it fails on an entry that has stopped being a root
+// and the retry starts from the fresh value it returns (hooking under a stale
+// root is harmless: that point is in the same component and has a smaller
+// index). The forest is fully written back when the kernel ends. Device-scope
+// reads instead go past the XCD's L2 on every step of every walk, which is
+// what the hooks of dense clusters spend their time on.
+__device__ __forceinline__ int32_t uf_ld(const int32_t *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void uf_st(int32_t *p, int32_t v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
 __device__ __forceinline__ int32_t uf_find(int32_t *P, int32_t x)
 {
-    int32_t p = ld_relaxed(P + x);
+    int32_t p = uf_ld(P + x);
     while (p != x) {
-        const int32_t gp = ld_relaxed(P + p);
+        const int32_t gp = uf_ld(P + p);
         if (gp == p)
             return p;
-        st_relaxed(P + x, gp);
+        uf_st(P + x, gp);
         x = gp;
-        p = ld_relaxed(P + x);
+        p = uf_ld(P + x);
     }
     return x;
 }
