@@ -6,7 +6,7 @@
 // instance (block prefix tables), so per-block counter reductions still
 // belong to one instance. The sequence contains kernel launches only, so it
 // can be recorded once into a HIP graph and replayed.
-#include "sng_internal.hpp"
+#include "sng_hook.hpp"
 
 namespace sng {
 
@@ -66,30 +66,13 @@ __global__ __launch_bounds__(256) void k_b_core_init(const Inst *__restrict__ T,
     batch_count(I.cnt, kCntCore, n_core);
 }
 
-__device__ __forceinline__ void b_hook_pair(const Inst &I, uint32_t a, uint32_t b)
-{
-    const bool ca = I.core[a], cb = I.core[b];
-    if (ca && cb)
-        uf_unite(I.labels, (int32_t)a, (int32_t)b);
-    else if (ca)
-        atomicMin(I.labels + b, (int32_t)a);
-    else if (cb)
-        atomicMin(I.labels + a, (int32_t)b);
-}
-
-// Hook of the accept words of one instance range, with block-local
-// compaction: a round scans 256 words (one per thread) and lists the
-// accepted slots in LDS, then all threads regenerate and hook them. Entry:
-// word offset in the round * 32 + bit (call in the word * 4 + Philox word).
-constexpr uint32_t kBHookWords = 256;
-
+// Hook of the accept words of one instance range, a round of
+// kHookRoundWords words at a time with block-local compaction.
 // Grid: total_wblocks rounded up to whole eighths; each XCD hooks a
 // contiguous eighth of the word blocks (xcd_block), so an instance's labels
 // and core flags stay in one L2.
 __global__ __launch_bounds__(256) void k_b_hook(const Inst *__restrict__ T, const BatchGeom G)
 {
-    __shared__ uint16_t list[kBHookWords * 32];
-    __shared__ uint32_t nlist;
     const uint32_t blk = xcd_block(blockIdx.x, gridDim.x);
     if (blk >= G.total_wblocks)
         return;  // block-uniform
@@ -98,28 +81,10 @@ __global__ __launch_bounds__(256) void k_b_hook(const Inst *__restrict__ T, cons
     const uint64_t words = I.chunks * 8ull;
     const uint64_t lo = (blk - G.wblk[k]) * kWordsPerBlock;
     const uint64_t hi = umin64(lo + kWordsPerBlock, words);
-    for (uint64_t w0 = lo; w0 < hi; w0 += kBHookWords) {  // block-uniform
-        if (threadIdx.x == 0)
-            nlist = 0;
-        const uint64_t w = w0 + threadIdx.x;
-        const uint32_t bits = (w < hi) ? I.mask[I.chunk0 * 8ull + w] : 0u;
-        if (!__syncthreads_or(bits != 0u))
-            continue;  // no accepted slot in this round (the list is not read)
-        uint32_t pos = list_reserve((uint32_t)__builtin_popcount(bits), &nlist);
-        for (uint32_t b = bits; b; b &= b - 1)
-            list[pos++] = (uint16_t)(threadIdx.x * 32u + (uint32_t)__builtin_ctz(b));
-        __syncthreads();
-        const uint32_t cnt = nlist;
-        for (uint32_t e = threadIdx.x; e < cnt; e += blockDim.x) {
-            const uint32_t v = list[e];
-            const uint64_t call = (w0 + (v >> 5)) * 8ull + ((v & 31u) >> 2);
-            const uint32_t i = (uint32_t)div_exact64(call, I.C, I.inv_C);
-            const uint32_t c = (uint32_t)(call - (uint64_t)i * I.C);
-            const Words4 W = philox10(c, i, I.key0, I.key1);
-            b_hook_pair(I, i, mod_exact(W.w[v & 3u], I.n, I.inv_n));
-        }
-        __syncthreads();  // the next round reuses the list
-    }
+    __shared__ uint16_t list[kHookRoundWords * 32];
+    __shared__ uint32_t nlist;
+    for (uint64_t w0 = lo; w0 < hi; w0 += kHookRoundWords)  // block-uniform
+        hook_round(I, w0, hi, list, &nlist);
 }
 
 __global__ __launch_bounds__(256) void k_b_compress(const Inst *__restrict__ T, const BatchGeom G)

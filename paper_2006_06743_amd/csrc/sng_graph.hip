@@ -12,7 +12,7 @@
 //              neighbour, or -1.
 // Roots are minimum indices whatever the order of the atomic operations, so
 // the result is deterministic.
-#include "sng_internal.hpp"
+#include "sng_hook.hpp"
 
 namespace sng {
 
@@ -77,20 +77,10 @@ __global__ __launch_bounds__(256) void k_core_init(Inst I)
     count_add(I.cnt, kCntCore, n_core);
 }
 
-__device__ __forceinline__ void hook_pair(const Inst &I, uint32_t a, uint32_t b)
-{
-    const bool ca = I.core[a], cb = I.core[b];
-    if (ca && cb)
-        uf_unite(I.labels, (int32_t)a, (int32_t)b);
-    else if (ca)
-        atomicMin(I.labels + b, (int32_t)a);
-    else if (cb)
-        atomicMin(I.labels + a, (int32_t)b);
-}
-
-// One thread per accept word (eight consecutive calls of the instance). At
-// the acceptance rates of single instances (a few percent of slots at most)
-// this beats listing the accepted slots first: most words hold none.
+// One thread per accept word (eight consecutive calls of the instance). This
+// beats listing the accepted slots of a block first (hook_round), also on
+// the 10k x 2 blobs where 6% of slots are accepted: unions into a few dense
+// clusters contend, and the list form runs more of them at once.
 __device__ __forceinline__ void hook_word(const Inst &I, uint64_t w)
 {
     const uint32_t bits = I.mask[I.chunk0 * 8ull + w];
@@ -184,7 +174,7 @@ hipError_t launch_hook_mask(const Inst &I, hipStream_t st)
 {
     if (I.chunks == 0)
         return hipSuccess;
-    hipLaunchKernelGGL(k_hook_mask, dim3(grid_for(I.chunks * 8ull, 256)), dim3(256), 0, st, I);
+hipLaunchKernelGGL(k_hook_mask, dim3(grid_for(I.chunks * 8ull, 256)), dim3(256), 0, st, I);
     return hipGetLastError();
 }
 
