@@ -46,6 +46,13 @@ def load() -> ctypes.CDLL:
     lib.sng_oracle_slot_sqdist.restype = ctypes.c_int
     lib.sng_oracle_dbscan.argtypes = [P, i64, i32, i64, i64, dbl, i32, u64, i32, P, P, P]
     lib.sng_oracle_dbscan.restype = ctypes.c_int
+    lib.sng_oracle_dot.argtypes = [P, i64, i32, i64, i64]
+    lib.sng_oracle_dot.restype = dbl
+    lib.sng_oracle_cosine.argtypes = [P, i64, i32, i64, i64]
+    lib.sng_oracle_cosine.restype = dbl
+    lib.sng_oracle_dbscan_similarity.argtypes = [P, i64, i32, i64, i64, i32, dbl, i32, u64, i32,
+                                                 P, P, P]
+    lib.sng_oracle_dbscan_similarity.restype = ctypes.c_int
     lib.sng_oracle_graph.argtypes = [i64, P, i64, i32, P, P, P]
     lib.sng_oracle_graph.restype = ctypes.c_int
     _lib = lib
@@ -111,6 +118,21 @@ def sqdist(X: np.ndarray, i: int, j: int) -> float:
     return float(load().sng_oracle_sqdist(_ptr(X), X.shape[1], X.shape[1], int(i), int(j)))
 
 
+DOT, COSINE = 1, 2  # similarity kinds (edge when the similarity is >= tau)
+
+
+def dot(X: np.ndarray, i: int, j: int) -> float:
+    """<x_i, x_j> in binary64, coordinate order."""
+    X = _rows(X)
+    return float(load().sng_oracle_dot(_ptr(X), X.shape[1], X.shape[1], int(i), int(j)))
+
+
+def cosine(X: np.ndarray, i: int, j: int) -> float:
+    """<x_i, x_j> / (|x_i| |x_j|) in binary64 (NaN for a zero row)."""
+    X = _rows(X)
+    return float(load().sng_oracle_cosine(_ptr(X), X.shape[1], X.shape[1], int(i), int(j)))
+
+
 def _rows(X: np.ndarray) -> np.ndarray:
     X = np.ascontiguousarray(X, dtype=np.float32)
     if X.ndim != 2:
@@ -164,6 +186,29 @@ def dbscan(X: np.ndarray, eps: float, min_pts: int, seed: int = 0, s: Optional[f
                                     int(seed), 1 if exhaustive else (2 if out_degree else 0),
                                     _ptr(labels), _ptr(deg),
                                     _ptr(st)), "sng_oracle_dbscan")
+    return _result(labels, deg, st)
+
+
+def dbscan_similarity(X: np.ndarray, kind: int, tau: float, min_pts: int, seed: int = 0,
+                      s: Optional[float] = None, m: Optional[int] = None,
+                      exhaustive: bool = False, out_degree: bool = False) -> Result:
+    """SNG-DBSCAN with a similarity query instead of the distance (Section 1):
+    an edge when the dot product (kind DOT) or the cosine (kind COSINE) of the
+    pair is >= tau. Sampling, modes and post-processing as in ``dbscan``."""
+    X = _rows(X)
+    n, d = X.shape
+    if not exhaustive and m is None:
+        m = samples_per_point(s, n)
+        if m < 0:
+            raise OracleError("invalid sampling rate")
+    labels = np.empty(n, np.int32)
+    deg = np.zeros(n, np.uint32)
+    st = np.zeros(8, np.uint64)
+    _check(load().sng_oracle_dbscan_similarity(_ptr(X), n, d, d, int(m or 0), int(kind),
+                                               float(tau), int(min_pts), int(seed),
+                                               1 if exhaustive else (2 if out_degree else 0),
+                                               _ptr(labels), _ptr(deg), _ptr(st)),
+           "sng_oracle_dbscan_similarity")
     return _result(labels, deg, st)
 
 

@@ -123,12 +123,64 @@ double sng_oracle_sqdist(const float *X, int64_t ld, int32_t d, int64_t i, int64
     return acc;
 }
 
-static int accepted(const float *X, int64_t ld, int32_t d, int64_t i, int64_t j, double eps2)
+/* ------------------------------------------------------------------------ */
+/* Similarity queries other than the distance (Section 1: the method only    */
+/* needs a yes/no similarity query per sampled pair, so any similarity      */
+/* function can define the edges). An edge joins i and j when their         */
+/* similarity is at least tau.                                              */
+/* ------------------------------------------------------------------------ */
+
+/* <x_i, x_j> in binary64, products and sums in coordinate order. */
+double sng_oracle_dot(const float *X, int64_t ld, int32_t d, int64_t i, int64_t j)
+{
+    const float *a = X + i * ld;
+    const float *b = X + j * ld;
+    double acc = 0.0;
+    for (int32_t k = 0; k < d; ++k) {
+        double p = (double)a[k] * (double)b[k];
+        acc = acc + p;
+    }
+    return acc;
+}
+
+/* <x_i, x_j> / (sqrt(<x_i, x_i>) * sqrt(<x_j, x_j>)) in binary64; NaN when a
+ * row is zero (0 / 0). */
+double sng_oracle_cosine(const float *X, int64_t ld, int32_t d, int64_t i, int64_t j)
+{
+    double ip = sng_oracle_dot(X, ld, d, i, j);
+    double ni = sqrt(sng_oracle_dot(X, ld, d, i, i));
+    double nj = sqrt(sng_oracle_dot(X, ld, d, j, j));
+    double den = ni * nj;
+    return ip / den;
+}
+
+/* The similarity query of a run: kind 0 is the paper's |x - x'| <= eps
+ * (squared, against eps2 = fl64(eps*eps)); kinds 1 and 2 accept when the dot
+ * product or the cosine is >= tau. */
+typedef struct {
+    int32_t kind;
+    double eps2;
+    double tau;
+} query;
+
+static int accepted(const float *X, int64_t ld, int32_t d, int64_t i, int64_t j, const query *q)
 {
     if (i == j)
         return 0;
-    double D = sng_oracle_sqdist(X, ld, d, i, j);
-    return D <= eps2; /* false for NaN */
+    switch (q->kind) {
+    case SNG_ORACLE_DOT:
+        return sng_oracle_dot(X, ld, d, i, j) >= q->tau; /* false for NaN */
+    case SNG_ORACLE_COSINE:
+        return sng_oracle_cosine(X, ld, d, i, j) >= q->tau;
+    default:
+        return sng_oracle_sqdist(X, ld, d, i, j) <= q->eps2;
+    }
+}
+
+static query distance_query(double eps)
+{
+    query q = {0, eps * eps, 0.0};
+    return q;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -176,11 +228,10 @@ static int valid_eps(double eps)
 /* Sampling step for sources [i0,i1): degrees (atomic integer adds, so the
  * result does not depend on thread order) and, optionally, the accepted
  * pairs gathered into *out (order irrelevant to everything downstream). */
-static int sample_graph(const float *X, int64_t n, int32_t d, int64_t ld, int64_t m, double eps,
-                        uint64_t seed, int64_t i0, int64_t i1, uint32_t *deg, uint64_t *stats,
-                        pairlist *out, int symmetrised)
+static int sample_graph(const float *X, int64_t n, int32_t d, int64_t ld, int64_t m,
+                        const query *q, uint64_t seed, int64_t i0, int64_t i1, uint32_t *deg,
+                        uint64_t *stats, pairlist *out, int symmetrised)
 {
-    const double eps2 = eps * eps;
     int nthreads = 1;
 #ifdef _OPENMP
     nthreads = omp_get_max_threads();
@@ -203,7 +254,7 @@ static int sample_graph(const float *X, int64_t n, int32_t d, int64_t ld, int64_
                     self_total++;
                     continue;
                 }
-                if (accepted(X, ld, d, i, j, eps2)) {
+                if (accepted(X, ld, d, i, j, q)) {
                     acc_total++;
 #pragma omp atomic
                     deg[i]++;
@@ -258,7 +309,8 @@ int sng_oracle_degrees_range(const float *X, int64_t n, int32_t d, int64_t ld, i
         return -1;
     if (n == 0)
         return 0;
-    return sample_graph(X, n, d, ld, m, eps, seed, i0, i1, deg, stats, NULL, 1);
+    const query q = distance_query(eps);
+    return sample_graph(X, n, d, ld, m, &q, seed, i0, i1, deg, stats, NULL, 1);
 }
 
 int sng_oracle_slot_sqdist(const float *X, int64_t n, int32_t d, int64_t ld, int64_t m,
@@ -365,13 +417,11 @@ static int postprocess(int64_t n, const pairlist *A, const uint32_t *deg, int32_
     return 0;
 }
 
-int sng_oracle_dbscan(const float *X, int64_t n, int32_t d, int64_t ld, int64_t m,
-                      double eps, int32_t min_pts, uint64_t seed, int32_t mode,
+/* The whole method for one similarity query (validated by the callers). */
+static int run_method(const float *X, int64_t n, int32_t d, int64_t ld, int64_t m,
+                      const query *q, int32_t min_pts, uint64_t seed, int32_t mode,
                       int32_t *labels, uint32_t *deg, uint64_t *stats)
 {
-    if (!valid_points(X, n, d, ld) || !valid_eps(eps) || mode < 0 || mode > 2 ||
-        (n > 0 && !labels) || (mode != 1 && m < 0))
-        return -1;
     if (mode != 1 && (m > 17179869184LL || (m > 0 && n > INT64_MAX / m)))
         return -2;
     uint64_t local[8] = {0};
@@ -385,13 +435,12 @@ int sng_oracle_dbscan(const float *X, int64_t n, int32_t d, int64_t ld, int64_t 
         /* mode 2: a point's degree counts only its own accepted samples (the
          * neighbour count of Lemma 2's proof); the graph is the same */
         if (n > 0)
-            rc = sample_graph(X, n, d, ld, m, eps, seed, 0, n, dg, local, &A, mode == 0);
+            rc = sample_graph(X, n, d, ld, m, q, seed, 0, n, dg, local, &A, mode == 0);
     } else {
-        /* exhaustive: the full eps-neighbourhood graph of classical DBSCAN */
-        const double eps2 = eps * eps;
+        /* exhaustive: the full neighbourhood graph of classical DBSCAN */
         for (int64_t i = 0; i < n && rc == 0; ++i)
             for (int64_t j = i + 1; j < n; ++j)
-                if (accepted(X, ld, d, i, j, eps2)) {
+                if (accepted(X, ld, d, i, j, q)) {
                     dg[i]++;
                     dg[j]++;
                     local[2]++;
@@ -409,6 +458,29 @@ int sng_oracle_dbscan(const float *X, int64_t n, int32_t d, int64_t ld, int64_t 
     if (rc == 0 && stats)
         memcpy(stats, local, sizeof(local));
     return rc;
+}
+
+int sng_oracle_dbscan(const float *X, int64_t n, int32_t d, int64_t ld, int64_t m,
+                      double eps, int32_t min_pts, uint64_t seed, int32_t mode,
+                      int32_t *labels, uint32_t *deg, uint64_t *stats)
+{
+    if (!valid_points(X, n, d, ld) || !valid_eps(eps) || mode < 0 || mode > 2 ||
+        (n > 0 && !labels) || (mode != 1 && m < 0))
+        return -1;
+    const query q = distance_query(eps);
+    return run_method(X, n, d, ld, m, &q, min_pts, seed, mode, labels, deg, stats);
+}
+
+int sng_oracle_dbscan_similarity(const float *X, int64_t n, int32_t d, int64_t ld, int64_t m,
+                                 int32_t kind, double tau, int32_t min_pts, uint64_t seed,
+                                 int32_t mode, int32_t *labels, uint32_t *deg, uint64_t *stats)
+{
+    if (!valid_points(X, n, d, ld) || (kind != SNG_ORACLE_DOT && kind != SNG_ORACLE_COSINE) ||
+        isnan(tau) || isinf(tau) || mode < 0 || mode > 2 || (n > 0 && !labels) ||
+        (mode != 1 && m < 0))
+        return -1;
+    const query q = {kind, 0.0, tau};
+    return run_method(X, n, d, ld, m, &q, min_pts, seed, mode, labels, deg, stats);
 }
 
 int sng_oracle_graph(int64_t n, const int64_t *edges, int64_t n_edges, int32_t min_pts,

@@ -50,6 +50,19 @@ uint32_t sng_oracle_partner(uint64_t seed, int64_t n, int64_t i, int64_t t);
 /* D(i,j): binary64 squared distance of rows i and j of X (row stride ld). */
 double sng_oracle_sqdist(const float *X, int64_t ld, int32_t d, int64_t i, int64_t j);
 
+/* Similarity functions other than the distance (Section 1: the method needs
+ * only a similarity query per sampled pair). An edge joins i and j when the
+ * similarity is >= tau (inclusive, NaN never accepted).
+ *   SNG_ORACLE_DOT:    <x_i, x_j>, products and sums in binary64 in
+ *                      coordinate order;
+ *   SNG_ORACLE_COSINE: <x_i, x_j> / (sqrt(<x_i, x_i>) * sqrt(<x_j, x_j>)),
+ *                      each part as for DOT, correctly rounded sqrt, product
+ *                      and quotient; a zero row gives NaN, so no edge. */
+#define SNG_ORACLE_DOT 1
+#define SNG_ORACLE_COSINE 2
+double sng_oracle_dot(const float *X, int64_t ld, int32_t d, int64_t i, int64_t j);
+double sng_oracle_cosine(const float *X, int64_t ld, int32_t d, int64_t i, int64_t j);
+
 /* stats[0..7] = slots, self_pairs, accepted, n_core, n_clusters, n_noise,
  * 0, 0.  Any of stats/deg may be NULL where noted. */
 
@@ -75,6 +88,13 @@ int sng_oracle_slot_sqdist(const float *X, int64_t n, int32_t d, int64_t ld, int
 int sng_oracle_dbscan(const float *X, int64_t n, int32_t d, int64_t ld, int64_t m,
                       double eps, int32_t min_pts, uint64_t seed, int32_t mode,
                       int32_t *labels, uint32_t *deg, uint64_t *stats);
+
+/* sng_oracle_dbscan with the similarity query `kind` (SNG_ORACLE_DOT or
+ * SNG_ORACLE_COSINE) against a finite tau instead of the distance against
+ * eps; modes, outputs and everything after the query as there. */
+int sng_oracle_dbscan_similarity(const float *X, int64_t n, int32_t d, int64_t ld, int64_t m,
+                                 int32_t kind, double tau, int32_t min_pts, uint64_t seed,
+                                 int32_t mode, int32_t *labels, uint32_t *deg, uint64_t *stats);
 
 /* Post-processing only, on an explicit accepted-pair list edges[2*k],
  * edges[2*k+1] (each pair counted once per occurrence, self-pairs rejected

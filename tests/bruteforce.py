@@ -21,9 +21,15 @@ def pairwise_sq(X: np.ndarray) -> np.ndarray:
 
 
 def dbscan_bruteforce(X: np.ndarray, eps: float, min_pts: int):
-    n = X.shape[0]
     D = pairwise_sq(X)
-    adj = D <= eps * eps
+    return dbscan_adjacency(D <= eps * eps, min_pts)
+
+
+def dbscan_adjacency(adj: np.ndarray, min_pts: int):
+    """DBSCAN on a given symmetric boolean neighbourhood matrix (the diagonal
+    is ignored)."""
+    adj = np.array(adj, dtype=bool)
+    n = adj.shape[0]
     np.fill_diagonal(adj, False)
     deg = adj.sum(axis=1)
     core = deg >= min_pts
