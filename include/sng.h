@@ -216,6 +216,37 @@ int sng_dbscan_lowp(const float *X, int64_t n, int32_t d, int64_t ld, const uint
                     int32_t min_pts, uint64_t seed, int32_t *labels, uint32_t *degrees,
                     void *workspace, size_t ws_bytes, const sng_config *cfg, void *stream);
 
+/* Similarity-threshold form of sng_dbscan. The method needs only a yes/no
+ * similarity query per sampled pair (Section 1), so the edge test of the
+ * sampling step may be a similarity at least tau instead of a distance at
+ * most eps:
+ *   SNG_SIM_DOT     <x_i, x_j> >= tau, the binary64 dot product summed in
+ *                   coordinate order without fused multiply-adds;
+ *   SNG_SIM_COSINE  <x_i, x_j> / (sqrt(<x_i,x_i>) * sqrt(<x_j,x_j>)) >= tau,
+ *                   each part as for SNG_SIM_DOT, IEEE square roots, product
+ *                   and quotient; a zero row has no cosine and no edge.
+ * Sampling, degrees, core points, components and borders are those of
+ * sng_dbscan. tau: any finite value (SNG_EINVAL otherwise); kind: one of the
+ * two above (SNG_EINVAL otherwise). The binary32 pass decides a pair from
+ * its squared distance and the two rows' norms (|a-b|^2 = |a|^2 + |b|^2 -
+ * 2<a,b>) with a band around the pair's threshold; pairs inside the band,
+ * and every pair of a row whose squared norm lies outside [2^-100, 2^100],
+ * are decided by the binary64 definition, so results equal the definition
+ * exactly. Workspace: sng_similarity_workspace_size (8 more bytes per point
+ * than sng_workspace_size; flags 0 or SNG_WS_DIRECT). cfg: launch shape,
+ * schedule and out_degree as for sng_dbscan; reuse_sample is not available
+ * (SNG_EINVAL). Stats: band_rel is the band's half-width relative to
+ * |x_i|^2 + |x_j|^2 + 2|threshold|. */
+typedef enum {
+    SNG_SIM_DOT = 1,
+    SNG_SIM_COSINE = 2
+} sng_similarity;
+int sng_similarity_workspace_size(int64_t n, int32_t d, int64_t m, int32_t flags, size_t *bytes);
+int sng_dbscan_similarity(const float *X, int64_t n, int32_t d, int64_t ld, double s,
+                          int32_t kind, double tau, int32_t min_pts, uint64_t seed,
+                          int32_t *labels, uint32_t *degrees, void *workspace, size_t ws_bytes,
+                          const sng_config *cfg, void *stream);
+
 /* Compact cluster ids. The method defines its clusters up to a renaming
  * (Section 4.1, Theorem 1); the clustering calls name each cluster by its
  * root, the smallest core index in it. out[i] = the rank of labels[i] among

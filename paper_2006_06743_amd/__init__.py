@@ -15,9 +15,11 @@ from typing import Optional, Sequence
 import torch
 
 from . import _lib
-from ._lib import SNG_BF16, SNG_FP16, SNG_FP32, SNGError, check, sng_config, sng_stats
+from ._lib import (SNG_BF16, SNG_FP16, SNG_FP32, SNG_SIM_COSINE, SNG_SIM_DOT, SNGError, check,
+                   sng_config, sng_stats)
 
-__all__ = ["dbscan", "dbscan_lowp", "degrees", "sample", "cluster", "compact_labels",
+__all__ = ["dbscan", "dbscan_lowp", "dbscan_similarity", "degrees", "sample", "cluster",
+           "compact_labels", "similarity_workspace_size", "SNG_SIM_DOT", "SNG_SIM_COSINE",
            "autotune", "autotune_lookup", "autotune_clear",
            "graph_labels", "sweep", "batch", "BatchPlan",
            "samples_per_point", "Config", "Stats", "SNGError", "SNG_FP32", "SNG_BF16",
@@ -197,6 +199,40 @@ def dbscan(X: torch.Tensor, s: float, eps: float, min_pts: int, seed: int,
                                  degrees_out.data_ptr() if degrees_out is not None else None,
                                  ws.data_ptr(), ws.numel(), _cfg(cfg), _stream(X)),
           "sng_dbscan")
+    return labels, degrees_out, ws
+
+
+def similarity_workspace_size(n: int, d: int, m: int, flags: int = 0) -> int:
+    b = ctypes.c_size_t()
+    check(_lib.load().sng_similarity_workspace_size(int(n), int(d), int(m), int(flags),
+                                                    ctypes.byref(b)),
+          "sng_similarity_workspace_size")
+    return b.value
+
+
+def dbscan_similarity(X: torch.Tensor, s: float, kind: int, tau: float, min_pts: int, seed: int,
+                      cfg: Optional[Config] = None, want_degrees: bool = True,
+                      labels: Optional[torch.Tensor] = None,
+                      degrees_out: Optional[torch.Tensor] = None,
+                      ws: Optional[torch.Tensor] = None):
+    """SNG-DBSCAN with a similarity query: an edge when the dot product
+    (SNG_SIM_DOT) or the cosine (SNG_SIM_COSINE) of a sampled pair is >= tau.
+    Returns (labels, degrees or None, ws)."""
+    n, d, ld = _rows(X)
+    m = samples_per_point(s, n)
+    if labels is None:
+        labels = torch.empty(n, dtype=torch.int32, device=X.device)
+    if want_degrees and degrees_out is None:
+        degrees_out = torch.empty(n, dtype=torch.int32, device=X.device)
+    if ws is None:
+        ws = _ws(similarity_workspace_size(n, d, m), X.device)
+    check(_lib.load().sng_dbscan_similarity(X.data_ptr(), n, d, ld, float(s), int(kind),
+                                            float(tau), int(min_pts), int(seed),
+                                            labels.data_ptr(),
+                                            degrees_out.data_ptr() if degrees_out is not None
+                                            else None,
+                                            ws.data_ptr(), ws.numel(), _cfg(cfg), _stream(X)),
+          "sng_dbscan_similarity")
     return labels, degrees_out, ws
 
 

@@ -14,6 +14,7 @@ LIB_PATH = os.path.join(HERE, "libsng.so")
 SNG_OK, SNG_EINVAL, SNG_ERANGE, SNG_EWORKSPACE, SNG_EHIP, SNG_EOVERFLOW, SNG_ENOTIMPL = \
     0, -1, -2, -3, -4, -5, -6
 SNG_FP32, SNG_BF16, SNG_FP16 = 0, 1, 2
+SNG_SIM_DOT, SNG_SIM_COSINE = 1, 2
 
 # Every symbol the header declares (checked by the CPU test suite).
 EXPORTS = [
@@ -24,6 +25,7 @@ EXPORTS = [
     "sng_sweep_workspace_size", "sng_dbscan_sweep", "sng_batch_workspace_size",
     "sng_dbscan_batch", "sng_batch_plan_create", "sng_batch_plan_launch",
     "sng_batch_plan_destroy", "sng_stats_read",
+    "sng_similarity_workspace_size", "sng_dbscan_similarity",
 ]
 
 
@@ -73,6 +75,9 @@ def load() -> ctypes.CDLL:
                        ctypes.c_int),
         "sng_dbscan_lowp": ([P, i64, i32, i64, P, i64, f32, i32, dbl, dbl, i32, u64, P, P, P,
                              sz, cfgp, P], ctypes.c_int),
+        "sng_similarity_workspace_size": ([i64, i32, i64, i32, ctypes.POINTER(sz)], ctypes.c_int),
+        "sng_dbscan_similarity": ([P, i64, i32, i64, dbl, i32, dbl, i32, u64, P, P, P, sz, cfgp,
+                                   P], ctypes.c_int),
         "sng_graph_workspace_size": ([i64, ctypes.POINTER(sz)], ctypes.c_int),
         "sng_graph_labels": ([i64, P, i64, i32, P, P, P, sz, P], ctypes.c_int),
         "sng_compact_labels": ([P, i64, P, P, P], ctypes.c_int),

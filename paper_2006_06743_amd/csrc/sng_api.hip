@@ -88,6 +88,12 @@ size_t plain_ws_bytes(int64_t n, int64_t m)
     return b;
 }
 
+// The similarity queries add two binary32 statistics per row.
+size_t sim_ws_bytes(int64_t n, int64_t m)
+{
+    return align_up(plain_ws_bytes(n, m) + (size_t)n * sizeof(float2));
+}
+
 // The mixed-precision pass adds per-row statistics and a queue of undecided
 // slots large enough for every slot, so it can never overflow.
 size_t lowp_ws_bytes(int64_t n, int64_t m)
@@ -276,16 +282,15 @@ int pick_bucket(const Inst &I, const sng_config *cfg, void *workspace, size_t ws
     return SNG_OK;
 }
 
-// Pass (a) plus post-processing for one carved instance.
+// Pass (a) plus post-processing for one carved instance. norms: the per-row
+// statistics array of a similarity instance (computed first), else null.
 int run_plain(Inst &I, const sng_config *cfg, bool labels_wanted, const BucketGeom *B,
-              hipStream_t st)
+              hipStream_t st, float2 *norms = nullptr)
 {
-    double band = 0.0;
-    {
-        float lo, hi;
-        band_fp32(I.eps2, I.d, &lo, &hi, &band);
-    }
-    SNG_TRY(init_header(I.cnt, (uint64_t)I.n * I.m, band, st, true));
+    // the plain layout keeps a stored partner-block sample valid
+    SNG_TRY(init_header(I.cnt, (uint64_t)I.n * I.m, I.band, st, norms == nullptr));
+    if (norms && I.m > 0)
+        SNG_TRY(launch_row_norms(I, norms, st));
     SNG_TRY(launch_fill_u32(I.deg, I.n, 0u, st));
     if (I.m > 0 && B) {
         SNG_TRY(launch_fill_u32(I.mask, I.chunks * 8, 0u, st));
@@ -596,6 +601,58 @@ int sng_dbscan(const float *X, int64_t n, int32_t d, int64_t ld, double s, doubl
     bool use = false;
     if ((rc = pick_bucket(I, cfg, workspace, ws_bytes, cv.off, &B, &use))) return rc;
     return run_plain(I, cfg, true, use ? &B : nullptr, st);
+}
+
+int sng_similarity_workspace_size(int64_t n, int32_t d, int64_t m, int32_t flags, size_t *bytes)
+{
+    if (!bytes || n < 0 || d < 1 || m < 0 || (flags & ~SNG_WS_DIRECT))
+        return SNG_EINVAL;
+    if (n > kMaxN || m > kMaxM)
+        return SNG_ERANGE;
+    size_t b = sim_ws_bytes(n, m);
+    BucketGeom g;
+    if (!(flags & SNG_WS_DIRECT) && bucket_geometry(n, d, m, true, &g))
+        b = align_up(b + bucket_bytes(g));
+    *bytes = b;
+    return SNG_OK;
+}
+
+int sng_dbscan_similarity(const float *X, int64_t n, int32_t d, int64_t ld, double s,
+                          int32_t kind, double tau, int32_t min_pts, uint64_t seed,
+                          int32_t *labels, uint32_t *degrees, void *workspace, size_t ws_bytes,
+                          const sng_config *cfg, void *stream)
+{
+    int rc = check_points(X, n, d, ld);
+    if (rc) return rc;
+    if (kind != SNG_SIM_DOT && kind != SNG_SIM_COSINE) return SNG_EINVAL;
+    if (isnan(tau) || isinf(tau)) return SNG_EINVAL;
+    if ((rc = check_cfg(cfg))) return rc;
+    if (cfg && cfg->reuse_sample) return SNG_EINVAL;  // the sample is not kept in this layout
+    int64_t m = 0;
+    if ((rc = m_from_s(s, n, &m))) return rc;
+    if (n > 0 && !labels) return SNG_EINVAL;
+    if (n > 0 && (((uintptr_t)labels & 3u) || ((uintptr_t)degrees & 3u))) return SNG_EINVAL;
+    const size_t need = sim_ws_bytes(n, m);
+    if (!workspace || ws_bytes < need) return SNG_EWORKSPACE;
+    hipStream_t st = (hipStream_t)stream;
+    Carve cv(workspace);
+    Inst I = make_inst(X, n, d, ld, m, 0.0, seed, min_pts);
+    I.out_deg = (cfg && cfg->out_degree) ? 1 : 0;
+    I.cnt = cv.take<unsigned long long>(kHeaderBytes / 8);
+    uint32_t *wdeg = cv.take<uint32_t>((size_t)n);
+    I.core = cv.take<uint8_t>((size_t)n);
+    I.mask = cv.take<uint32_t>(sizes_for(n, m).chunks * 8);
+    float2 *norms = cv.take<float2>((size_t)n);
+    I.deg = degrees ? degrees : wdeg;
+    I.labels = labels;
+    set_similarity(I, kind, tau, norms);
+    sng_config tuned;
+    cfg = effective_cfg(I, cfg, &tuned);
+    BucketGeom B;
+    bool use = false;
+    if ((rc = pick_bucket(I, cfg, workspace, ws_bytes, cv.off, &B, &use, kLayoutSimilarity)))
+        return rc;
+    return run_plain(I, cfg, true, use ? &B : nullptr, st, norms);
 }
 
 int sng_dbscan_lowp(const float *X, int64_t n, int32_t d, int64_t ld, const uint16_t *X_lp,

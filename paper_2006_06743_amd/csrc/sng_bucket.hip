@@ -31,7 +31,10 @@ constexpr uint32_t kRecOffShift = 18;  // record: call offset (14 bits) | word (
 
 // Decisions take point indices; row pointers for the binary64 recheck are
 // formed only inside the band. record() receives the slot's global call
-// number as a functor, evaluated only for accepted slots.
+// number as a functor, evaluated only for accepted slots. kSim: the
+// instance's similarity query instead of the distance (per-pair band on the
+// same binary32 distance).
+template <bool kSim>
 struct BucketPlainPolicy {
     int out_deg;  // 1: out-degrees (no partner-side count)
     const float *X;
@@ -41,15 +44,24 @@ struct BucketPlainPolicy {
     uint32_t *mask;
     float lo, hi;
     double eps2;
+    SimQuery sim;
 
     __device__ __forceinline__ int decide(float F, uint32_t i, uint32_t j, Tally &t, int q)
     {
-        if (F <= lo)
-            return 1;
-        if (F > hi)
-            return 0;
-        t.rechecked += (q == 0);
-        return sqdist_f64(X + (int64_t)i * ld, X + (int64_t)j * ld, d) <= eps2;
+        if constexpr (kSim) {
+            const int r = sim.band(i, j, F);
+            if (r >= 0)
+                return r;
+            t.rechecked += (q == 0);
+            return sim_accept_f64(X + (int64_t)i * ld, X + (int64_t)j * ld, d, sim.kind, sim.tau);
+        } else {
+            if (F <= lo)
+                return 1;
+            if (F > hi)
+                return 0;
+            t.rechecked += (q == 0);
+            return sqdist_f64(X + (int64_t)i * ld, X + (int64_t)j * ld, d) <= eps2;
+        }
     }
     template <class CallFn>
     __device__ __forceinline__ void record(int acc, uint32_t i, uint32_t j, CallFn call_of, int w,
@@ -454,12 +466,12 @@ __device__ __forceinline__ void eval_all(const Inst &I, const BucketGeom &B, Pol
     }
 }
 
-template <class Row, int OB, bool kBuf>
+template <class Row, int OB, bool kBuf, bool kSim>
 __global__ __launch_bounds__(256) void k_bkt_eval_plain(Inst I, BucketGeom B)
 {
     if (!sample_ok(I, B))
         return;
-    BucketPlainPolicy pol;
+    BucketPlainPolicy<kSim> pol;
     pol.out_deg = I.out_deg;
     pol.X = I.X;
     pol.ld = I.ld;
@@ -469,6 +481,7 @@ __global__ __launch_bounds__(256) void k_bkt_eval_plain(Inst I, BucketGeom B)
     pol.lo = I.lo;
     pol.hi = I.hi;
     pol.eps2 = I.eps2;
+    pol.sim = I.sim;
     Tally t;
     eval_all<Row, OB, kBuf>(I, B, pol, t);
     commit_tally(t, I.cnt);
@@ -620,11 +633,18 @@ hipError_t launch_bucket_plain(const Inst &I, const BucketGeom &B0, const PassAS
     const bool vec_ok = ((uintptr_t)I.X % 16 == 0) && (I.ld % 4 == 0);
     return dispatch(I.d, vec_ok, sh, [&]<class Row, int OB>(uint32_t) -> hipError_t {
         if constexpr (Row::kPrefetch) {
-            if (use_buffer(I))
-                hipLaunchKernelGGL((k_bkt_eval_plain<Row, OB, true>), dim3(eval_blocks(B)),
+            const bool buf = use_buffer(I), sim = I.sim.kind != kSimNone;
+            if (buf && !sim)
+                hipLaunchKernelGGL((k_bkt_eval_plain<Row, OB, true, false>), dim3(eval_blocks(B)),
+                                   dim3(256), 0, st, I, B);
+            else if (!sim)
+                hipLaunchKernelGGL((k_bkt_eval_plain<Row, OB, false, false>),
+                                   dim3(eval_blocks(B)), dim3(256), 0, st, I, B);
+            else if (buf)
+                hipLaunchKernelGGL((k_bkt_eval_plain<Row, OB, true, true>), dim3(eval_blocks(B)),
                                    dim3(256), 0, st, I, B);
             else
-                hipLaunchKernelGGL((k_bkt_eval_plain<Row, OB, false>), dim3(eval_blocks(B)),
+                hipLaunchKernelGGL((k_bkt_eval_plain<Row, OB, false, true>), dim3(eval_blocks(B)),
                                    dim3(256), 0, st, I, B);
             return hipGetLastError();
         } else {

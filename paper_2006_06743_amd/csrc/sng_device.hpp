@@ -26,6 +26,47 @@ enum Counter : int {
     kCntNum = 16
 };
 
+// Similarity queries other than the distance: an edge when the dot product
+// (kSimDot) or the cosine (kSimCos) of the pair is at least tau; binary64 in
+// coordinate order decides, as for the distance. The binary32 pass still
+// computes the squared distance F: by polarisation <a,b> = (|a|^2 + |b|^2 -
+// |a-b|^2) / 2, so the dot product reaches t exactly when |a-b|^2 <= |a|^2 +
+// |b|^2 - 2t, a threshold of the pair (t = tau, or tau |a||b| for the cosine).
+//
+// Band: with K = |a|^2 + |b|^2 + 2|t|, the binary32 F is within 2a*K + beta
+// of |a-b|^2 (a = gamma_{d+2} of binary32, |a-b|^2 <= 2K), the binary64 dot
+// product within gamma_d(binary64)*K/2 of the exact one, and the cosine's
+// quotient, product and square roots add relative errors of order d*2^-53.
+// The threshold is formed in binary32 from per-row norms rounded to binary32
+// (within 2^-23 relative), which costs a few binary32 units of K more. k
+// below is 2a + 2^-19 rounded up, which covers all of it with margin: F below
+// E - H is surely an edge, F above E + H surely not.
+enum : int32_t { kSimNone = 0, kSimDot = 1, kSimCos = 2 };
+
+struct SimQuery {
+    const float2 *nrm;  // [n] per row {fl32 |x|^2, fl32 |x|}; NaN sends the row's pairs to binary64
+    int32_t kind;       // kSimNone: the distance query (the other fields unused)
+    float t;            // fl32(tau)
+    float k;            // relative half-width of the band (times K)
+    float beta;         // absolute half-width (flushed binary32 subnormals)
+    double tau;         // the threshold of the binary64 definition
+
+    // 1: surely an edge, 0: surely not, -1: undecided (NaN operands included)
+    __device__ __forceinline__ int band(uint32_t i, uint32_t j, float F) const
+    {
+        const float2 a = nrm[i], b = nrm[j];
+        const float t2 = 2.0f * (kind == kSimCos ? t * (a.y * b.y) : t);
+        const float A = a.x + b.x;
+        const float E = A - t2;
+        const float H = k * (A + __builtin_fabsf(t2)) + beta;
+        if (F <= E - H)
+            return 1;
+        if (F > E + H)
+            return 0;
+        return -1;
+    }
+};
+
 // One clustering instance as the kernels see it.
 struct Inst {
     const float *X;         // row-major, element (i,k) at X[i*ld + k]
@@ -50,6 +91,7 @@ struct Inst {
     int32_t min_pts;
     int32_t out_deg;        // 1: a point's degree counts only its own accepted samples
     double band;              // relative half-width of the binary32 band (reported)
+    SimQuery sim;           // kind kSimNone: the distance against eps2
 };
 
 // ---------------------------------------------------------------------------
@@ -303,6 +345,34 @@ __device__ __noinline__ double sqdist_f64(const float *__restrict__ a, const flo
         acc = acc + sq;
     }
     return acc;
+}
+
+// The binary64 definitions of the similarity queries: the dot product in
+// coordinate order, and the cosine ip / (sqrt(|a|^2) * sqrt(|b|^2)) with each
+// squared norm summed the same way (0 / 0 for a zero row: no edge).
+__device__ __noinline__ int sim_accept_f64(const float *__restrict__ a,
+                                           const float *__restrict__ b, int d, int kind,
+                                           double tau)
+{
+#pragma clang fp contract(off)
+    double ip = 0.0;
+    for (int k = 0; k < d; ++k) {
+        const double p = (double)a[k] * (double)b[k];
+        ip = ip + p;
+    }
+    if (kind == kSimDot)
+        return ip >= tau;
+    double na = 0.0, nb = 0.0;
+    for (int k = 0; k < d; ++k) {
+        const double p = (double)a[k] * (double)a[k];
+        na = na + p;
+    }
+    for (int k = 0; k < d; ++k) {
+        const double p = (double)b[k] * (double)b[k];
+        nb = nb + p;
+    }
+    const double den = __builtin_sqrt(na) * __builtin_sqrt(nb);
+    return ip / den >= tau;
 }
 
 // ---------------------------------------------------------------------------

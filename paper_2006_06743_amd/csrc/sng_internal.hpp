@@ -99,6 +99,7 @@ constexpr int kSampleHdr = 32;
 // the layout that drew it.
 constexpr uint32_t kLayoutPlain = 1;
 constexpr uint32_t kLayoutSweep = 2;
+constexpr uint32_t kLayoutSimilarity = 3;
 uint64_t sample_tag(int64_t n, int64_t m, uint64_t seed, uint32_t bshift, uint32_t layout);
 bool bucket_geometry(int64_t n, int d, int64_t m, bool force, BucketGeom *g);
 size_t bucket_bytes(const BucketGeom &g);
@@ -121,6 +122,11 @@ hipError_t launch_pass_a(const Inst &I, const PassAShape &sh, hipStream_t st);
 hipError_t launch_pass_a_batch(const Inst *table, int count, const uint64_t *chunk_starts,
                                uint64_t total_chunks, int d, bool vec_ok, const PassAShape &sh,
                                hipStream_t st);
+
+// Similarity queries: fills I.sim for kind (kSimDot, kSimCos) and tau, with
+// nrm the caller-carved [n] array that launch_row_norms writes.
+void set_similarity(Inst &I, int32_t kind, double tau, float2 *nrm);
+hipError_t launch_row_norms(const Inst &I, float2 *nrm, hipStream_t st);
 
 // Post-processing kernels (core mask, hooks, finalize).
 hipError_t launch_fill_u32(uint32_t *p, uint64_t count, uint32_t v, hipStream_t st);

@@ -26,11 +26,15 @@ namespace sng {
 // Plain decision: accept iff the binary32 distance is surely below the band,
 // or the binary64 recheck accepts. Accepted slots add to both degrees and set
 // their accept bit (kept per call: four bits per lane, eight lanes per word).
+// kSim: the similarity query of the instance instead, through its per-pair
+// band on the same binary32 distance.
+template <bool kSim>
 struct PlainPolicy {
     uint32_t *deg;
     uint32_t *mask;
     float lo, hi;
     double eps2;
+    SimQuery sim;
     int out_deg = 0;     // 1: out-degrees (no partner-side count)
     uint32_t deg_i = 0;  // accepted slots of the cached source row
     uint32_t nib = 0;    // accept bits of this lane's own call
@@ -42,15 +46,23 @@ struct PlainPolicy {
             atomicAdd(deg + src, deg_i);
         deg_i = 0;
     }
-    __device__ __forceinline__ int decide(float F, const float *rowi, const float *rowj, int d,
-                                          Tally &t, int q)
+    __device__ __forceinline__ int decide(float F, uint32_t i, uint32_t j, const float *rowi,
+                                          const float *rowj, int d, Tally &t, int q)
     {
-        if (F <= lo)
-            return 1;
-        if (F > hi)
-            return 0;
-        t.rechecked += (q == 0);
-        return sqdist_f64(rowi, rowj, d) <= eps2;
+        if constexpr (kSim) {
+            const int r = sim.band(i, j, F);
+            if (r >= 0)
+                return r;
+            t.rechecked += (q == 0);
+            return sim_accept_f64(rowi, rowj, d, sim.kind, sim.tau);
+        } else {
+            if (F <= lo)
+                return 1;
+            if (F > hi)
+                return 0;
+            t.rechecked += (q == 0);
+            return sqdist_f64(rowi, rowj, d) <= eps2;
+        }
     }
     __device__ __forceinline__ void record(int acc, uint32_t, uint32_t j, int q, int o, int w,
                                            Tally &t)
@@ -76,19 +88,21 @@ struct PlainPolicy {
     }
 };
 
-__device__ __forceinline__ PlainPolicy plain_policy(const Inst &I)
+template <bool kSim>
+__device__ __forceinline__ PlainPolicy<kSim> plain_policy(const Inst &I)
 {
-    PlainPolicy p;
+    PlainPolicy<kSim> p;
     p.deg = I.deg;
     p.mask = I.mask;
     p.lo = I.lo;
     p.hi = I.hi;
     p.eps2 = I.eps2;
+    p.sim = I.sim;
     p.out_deg = I.out_deg;
     return p;
 }
 
-template <class Row, int OB>
+template <class Row, int OB, bool kSim>
 __global__ __launch_bounds__(256) void k_pass_a(Inst I, uint32_t cpw, uint32_t slice_floats)
 {
     extern __shared__ float lds[];
@@ -96,7 +110,7 @@ __global__ __launch_bounds__(256) void k_pass_a(Inst I, uint32_t cpw, uint32_t s
     const uint64_t lo = wave * cpw;
     float *slice = lds + (threadIdx.x / kWave) * slice_floats;
     Tally t;
-    PlainPolicy pol = plain_policy(I);
+    PlainPolicy<kSim> pol = plain_policy<kSim>(I);
     if (lo < I.chunks)  // wave-uniform
         pass_a_range<Row, OB>(I, pol, lo, min(lo + cpw, I.chunks), slice, t);
     commit_tally(t, I.cnt);
@@ -130,7 +144,7 @@ __global__ __launch_bounds__(256) void k_pass_a_batch(const Inst *__restrict__ t
         const Inst I = table[a];
         const uint64_t end = min(hi, starts[a + 1]);
         Tally t;
-        PlainPolicy pol = plain_policy(I);
+        PlainPolicy<false> pol = plain_policy<false>(I);
         pass_a_range<Row, OB>(I, pol, lo - starts[a], end - starts[a], slice, t);
         commit_tally_wave(t, I.cnt);
         lo = end;
@@ -224,8 +238,14 @@ hipError_t go(const Inst &I, const PassAShape &sh, uint32_t slice, hipStream_t s
     if (blocks > 0x7FFFFFFFull)
         return hipErrorInvalidValue;
     const size_t lds = (size_t)slice * sizeof(float) * sh.waves_per_block;
-    hipLaunchKernelGGL((k_pass_a<Row, OB>), dim3((unsigned)blocks), dim3(64 * sh.waves_per_block),
-                       lds, st, I, (uint32_t)sh.chunks_per_wave, slice);
+    if (I.sim.kind != kSimNone)
+        hipLaunchKernelGGL((k_pass_a<Row, OB, true>), dim3((unsigned)blocks),
+                           dim3(64 * sh.waves_per_block), lds, st, I, (uint32_t)sh.chunks_per_wave,
+                           slice);
+    else
+        hipLaunchKernelGGL((k_pass_a<Row, OB, false>), dim3((unsigned)blocks),
+                           dim3(64 * sh.waves_per_block), lds, st, I, (uint32_t)sh.chunks_per_wave,
+                           slice);
     return hipGetLastError();
 }
 

@@ -227,7 +227,7 @@ struct Tally {
 // decision is, and what it updates, is the policy's business (Pol):
 //   begin_chunk()                 per chunk, before any slot
 //   flush_source(src, q)          the group leaves source row src
-//   decide(F, rowi, rowj, d, t, q)  group-uniform result for one slot
+//   decide(F, i, j, rowi, rowj, d, t, q)  group-uniform result for one slot
 //   record(r, i, j, q, o, w, t)   account one decided slot (call o, word w)
 //   end_chunk(global_chunk, lane) per chunk, after every slot
 // Every cross-lane operation happens under group-uniform control flow.
@@ -317,7 +317,8 @@ __device__ __forceinline__ void pass_a_range(const Inst &I, Pol &pol, uint64_t c
                         buf[b][w] = Row::fetch(rowj, q, d);
                     float F = group_sum<G>(xi.partial(buf[b][w], q, d));
                     F = __int_as_float((int)group_bcast<G>((uint32_t)__float_as_int(F), 0));
-                    const int r = pol.decide(F, X + (int64_t)io[b] * ld, rowj, d, tally, q);
+                    const int r =
+                        pol.decide(F, io[b], jw, X + (int64_t)io[b] * ld, rowj, d, tally, q);
                     pol.record(r, io[b], jw, q, o, w, tally);
                 }
             }

@@ -34,8 +34,8 @@ struct SweepPolicy {
 
     __device__ __forceinline__ void begin_chunk() { own = 0x01010101u * (uint32_t)K; }
     __device__ __forceinline__ void flush_source(uint32_t, int) {}
-    __device__ __forceinline__ int decide(float F, const float *rowi, const float *rowj, int d,
-                                          Tally &t, int q)
+    __device__ __forceinline__ int decide(float F, uint32_t, uint32_t, const float *rowi,
+                                          const float *rowj, int d, Tally &t, int q)
     {
         if (!(F <= hi_max))
             return K;  // beyond every band (or NaN): rejected at every level

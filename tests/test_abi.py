@@ -139,3 +139,31 @@ def test_autotune_arguments_and_cache(lib):
     out = sng_config()
     assert lib.sng_autotune_lookup(fake, 10, 2, 2, 5, ctypes.byref(out)) == -6
     assert lib.sng_autotune_lookup(fake, 10, 2, 2, 5, None) == -1
+
+
+def test_similarity_arguments_rejected_before_launch(lib):
+    from paper_2006_06743_amd._lib import sng_config
+    fake = ctypes.c_void_p(0x1000)
+    ws = ctypes.c_void_p(0x2000)
+    lab = ctypes.c_void_p(0x3000)
+
+    def call(**kw):
+        return lib.sng_dbscan_similarity(kw.get("X", fake), kw.get("n", 10), kw.get("d", 2),
+                                         kw.get("ld", 2), kw.get("s", 0.5), kw.get("kind", 2),
+                                         kw.get("tau", 0.5), 3, 1, kw.get("labels", lab), None,
+                                         kw.get("ws", ws), kw.get("wsb", 0), kw.get("cfg"), None)
+    assert call(kind=0) == -1 and call(kind=3) == -1
+    assert call(tau=float("nan")) == -1
+    assert call(tau=float("inf")) == -1 and call(tau=float("-inf")) == -1
+    assert call(d=0) == -1 and call(ld=1) == -1 and call(n=2**31) == -2
+    assert call(s=-1.0) == -1 and call(labels=None) == -1
+    assert call(wsb=10) == -3
+    assert call(cfg=ctypes.byref(sng_config(0, 0, 0, 0, 0, 1))) == -1  # reuse_sample
+    # workspace: 8 more bytes per point than the distance form
+    b, c = ctypes.c_size_t(), ctypes.c_size_t()
+    assert lib.sng_similarity_workspace_size(1000, 16, 50, 0x100, ctypes.byref(b)) == 0
+    assert lib.sng_workspace_size(1000, 16, 50, 0x100, ctypes.byref(c)) == 0
+    assert c.value + 8 * 1000 <= b.value <= c.value + 8 * 1000 + 256
+    assert lib.sng_similarity_workspace_size(1000, 16, 50, 1, ctypes.byref(b)) == -1
+    assert lib.sng_similarity_workspace_size(-1, 16, 50, 0, ctypes.byref(b)) == -1
+    assert lib.sng_similarity_workspace_size(2**31, 16, 50, 0, ctypes.byref(b)) == -2
