@@ -10,7 +10,7 @@ kernel, the oracle's CPU rate on a bounded sample, and the plain-vs-mixed,
 plain-vs-sweep and sequential-vs-batched comparisons.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--schedule auto|direct]
-                    [--forms small,mixed,sweep,batch,lidar,recovery | --no-forms]
+                    [--forms small,mixed,sweep,batch,lidar,recovery,similarity | --no-forms]
                     [--no-cpu-baseline]
                     [--calibrate-copy]
 """
@@ -32,7 +32,8 @@ METRIC = "sampled pair-distance evals/sec + end-to-end cluster time (plain vs mi
 KERNELS = {
     "partner": {"name": "k_bkt_eval_plain (partner-block evaluate)",
                 "traffic": os.path.join(ROOT, "profiles", "bkt_eval_gmm16d_traffic.json"),
-                "sources": ["paper_2006_06743_amd/csrc/sng_bucket.hip",
+                "sources": ["paper_2006_06743_amd/csrc/sng_bucket_eval.hpp",
+                            "paper_2006_06743_amd/csrc/sng_bucket_eval_dist.hip",
                             "paper_2006_06743_amd/csrc/sng_pass_a.hpp",
                             "paper_2006_06743_amd/csrc/sng_device.hpp"]},
     "direct": {"name": "k_pass_a (direct-gather sampled-distance pass)",
@@ -274,10 +275,40 @@ def form_lidar(sng, torch, wl, reps):
             "alg_gbs": alg / ((t_sample + t_eval) * 1e-3) / 1e9}
 
 
+def form_similarity(sng, torch, wl, reps):
+    """Similarity-threshold edges against the distance form on the same
+    slots: cosine >= 0.95 and dot product >= 300 on the 1e6 x 16 mixture
+    (partner blocks), cosine >= 0.9 on the 70k x 784 images."""
+    out = {}
+    for W, kind, tau, min_pts in [
+            (wl.mixture_16d(), sng.SNG_SIM_COSINE, 0.95, None),
+            (wl.mixture_16d(), sng.SNG_SIM_DOT, 300.0, None),
+            (wl.mnistlike_784d(), sng.SNG_SIM_COSINE, 0.9, 10)]:
+        mp = W.min_pts if min_pts is None else min_pts
+        X = torch.from_numpy(W.X).cuda()
+        slots = W.n * sng.samples_per_point(W.s, W.n)
+        lab, deg, ws = sng.dbscan_similarity(X, W.s, kind, tau, mp, W.seed)
+        t_sim = _cuda_ms(torch, lambda: sng.dbscan_similarity(
+            X, W.s, kind, tau, mp, W.seed, labels=lab, degrees_out=deg, ws=ws), reps)
+        st = sng.stats(ws)
+        lab2, deg2, ws2 = sng.dbscan(X, W.s, W.eps, mp, W.seed)
+        t_dist = _cuda_ms(torch, lambda: sng.dbscan(X, W.s, W.eps, mp, W.seed, labels=lab2,
+                                                    degrees_out=deg2, ws=ws2), reps)
+        name = "cosine" if kind == sng.SNG_SIM_COSINE else "dot"
+        out["%s_%s" % (W.name, name)] = {
+            "query": "%s >= %g" % (name, tau), "slots": slots, "similarity_ms": t_sim,
+            "distance_ms": t_dist, "pair_evals_per_s": slots / (t_sim * 1e-3),
+            "recheck_fraction": st.rechecked / max(st.slots, 1), "accepted": st.accepted,
+            "clusters": st.n_clusters}
+        del X, lab, deg, ws, lab2, deg2, ws2
+        torch.cuda.empty_cache()
+    return out
+
+
 FORMS = {"mixed": ("mixed_precision", form_mixed), "sweep": ("sweep", form_sweep),
          "batch": ("batch", form_batch),
          "recovery": ("recovery", form_recovery), "small": ("small", form_small),
-         "lidar": ("lidar", form_lidar)}
+         "lidar": ("lidar", form_lidar), "similarity": ("similarity", form_similarity)}
 
 
 def time_forms(sng, torch, wl, which, reps=3):
@@ -300,7 +331,7 @@ def main():
     ap.add_argument("--schedule", choices=["tuned", "auto", "direct"], default="tuned",
                     help="tuned: the autotuner's choice (timed before the run); auto: the "
                          "library's rule (partner blocks here); direct: direct gathers")
-    ap.add_argument("--forms", default="small,mixed,sweep,batch,lidar,recovery",
+    ap.add_argument("--forms", default="small,mixed,sweep,batch,lidar,recovery,similarity",
                     help="comma-separated subset of small, mixed, sweep, batch, lidar, "
                          "recovery")
     ap.add_argument("--no-forms", action="store_true")

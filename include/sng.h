@@ -227,21 +227,27 @@ int sng_dbscan_lowp(const float *X, int64_t n, int32_t d, int64_t ld, const uint
  *                   and quotient; a zero row has no cosine and no edge.
  * Sampling, degrees, core points, components and borders are those of
  * sng_dbscan. tau: any finite value (SNG_EINVAL otherwise); kind: one of the
- * two above (SNG_EINVAL otherwise). The binary32 pass decides a pair from
- * its squared distance and the two rows' norms (|a-b|^2 = |a|^2 + |b|^2 -
- * 2<a,b>) with a band around the pair's threshold; pairs inside the band,
- * and every pair of a row whose squared norm lies outside [2^-100, 2^100],
- * are decided by the binary64 definition, so results equal the definition
- * exactly. Workspace: sng_similarity_workspace_size (8 more bytes per point
- * than sng_workspace_size; flags 0 or SNG_WS_DIRECT). cfg: launch shape,
- * schedule and out_degree as for sng_dbscan; reuse_sample is not available
- * (SNG_EINVAL). Stats: band_rel is the band's half-width relative to
- * |x_i|^2 + |x_j|^2 + 2|threshold|. */
+ * two above (SNG_EINVAL otherwise). The binary32 pass filters with a
+ * squared distance: for the cosine on a unit-length copy of the rows (kept
+ * in the workspace), where cos >= tau is |u - v|^2 <= 2 - 2 tau; for the dot
+ * product on the rows themselves against the pair's threshold |x_i|^2 +
+ * |x_j|^2 - 2 tau (polarisation), from squared norms kept in the workspace.
+ * Pairs within the filter's error bound of the threshold, and every pair of
+ * a row whose squared norm lies outside [2^-100, 2^100], are decided by the
+ * binary64 definition on the caller's rows, so results equal the definition
+ * exactly. Workspace: sng_similarity_workspace_size for the same kind
+ * (flags 0 or SNG_WS_DIRECT as for sng_workspace_size; the cosine adds
+ * 4 * n * (d rounded up to a multiple of 4) bytes, the dot product 4 * n).
+ * cfg: launch shape, schedule and out_degree as for sng_dbscan; reuse_sample
+ * is not available (SNG_EINVAL). Stats: band_rel is the filter's half-width
+ * (cosine: absolute on |u - v|^2; dot product: relative to |x_i|^2 + |x_j|^2
+ * + 2|tau|). */
 typedef enum {
     SNG_SIM_DOT = 1,
     SNG_SIM_COSINE = 2
 } sng_similarity;
-int sng_similarity_workspace_size(int64_t n, int32_t d, int64_t m, int32_t flags, size_t *bytes);
+int sng_similarity_workspace_size(int64_t n, int32_t d, int64_t m, int32_t kind, int32_t flags,
+                                  size_t *bytes);
 int sng_dbscan_similarity(const float *X, int64_t n, int32_t d, int64_t ld, double s,
                           int32_t kind, double tau, int32_t min_pts, uint64_t seed,
                           int32_t *labels, uint32_t *degrees, void *workspace, size_t ws_bytes,

@@ -202,10 +202,10 @@ def dbscan(X: torch.Tensor, s: float, eps: float, min_pts: int, seed: int,
     return labels, degrees_out, ws
 
 
-def similarity_workspace_size(n: int, d: int, m: int, flags: int = 0) -> int:
+def similarity_workspace_size(n: int, d: int, m: int, kind: int, flags: int = 0) -> int:
     b = ctypes.c_size_t()
-    check(_lib.load().sng_similarity_workspace_size(int(n), int(d), int(m), int(flags),
-                                                    ctypes.byref(b)),
+    check(_lib.load().sng_similarity_workspace_size(int(n), int(d), int(m), int(kind),
+                                                    int(flags), ctypes.byref(b)),
           "sng_similarity_workspace_size")
     return b.value
 
@@ -225,7 +225,7 @@ def dbscan_similarity(X: torch.Tensor, s: float, kind: int, tau: float, min_pts:
     if want_degrees and degrees_out is None:
         degrees_out = torch.empty(n, dtype=torch.int32, device=X.device)
     if ws is None:
-        ws = _ws(similarity_workspace_size(n, d, m), X.device)
+        ws = _ws(similarity_workspace_size(n, d, m, kind), X.device)
     check(_lib.load().sng_dbscan_similarity(X.data_ptr(), n, d, ld, float(s), int(kind),
                                             float(tau), int(min_pts), int(seed),
                                             labels.data_ptr(),

@@ -75,7 +75,8 @@ def load() -> ctypes.CDLL:
                        ctypes.c_int),
         "sng_dbscan_lowp": ([P, i64, i32, i64, P, i64, f32, i32, dbl, dbl, i32, u64, P, P, P,
                              sz, cfgp, P], ctypes.c_int),
-        "sng_similarity_workspace_size": ([i64, i32, i64, i32, ctypes.POINTER(sz)], ctypes.c_int),
+        "sng_similarity_workspace_size": ([i64, i32, i64, i32, i32, ctypes.POINTER(sz)],
+                                          ctypes.c_int),
         "sng_dbscan_similarity": ([P, i64, i32, i64, dbl, i32, dbl, i32, u64, P, P, P, sz, cfgp,
                                    P], ctypes.c_int),
         "sng_graph_workspace_size": ([i64, ctypes.POINTER(sz)], ctypes.c_int),

@@ -88,10 +88,16 @@ size_t plain_ws_bytes(int64_t n, int64_t m)
     return b;
 }
 
-// The similarity queries add two binary32 statistics per row.
-size_t sim_ws_bytes(int64_t n, int64_t m)
+// The similarity queries add per-row data: the binary32 squared norm (dot
+// product) or a unit-length copy of the row (cosine).
+size_t sim_rows_floats(int64_t n, int32_t d, int32_t kind)
 {
-    return align_up(plain_ws_bytes(n, m) + (size_t)n * sizeof(float2));
+    return (size_t)n * (kind == SNG_SIM_COSINE ? (size_t)unit_copy_ld(d) : 1u);
+}
+
+size_t sim_ws_bytes(int64_t n, int32_t d, int64_t m, int32_t kind)
+{
+    return align_up(plain_ws_bytes(n, m) + sim_rows_floats(n, d, kind) * sizeof(float));
 }
 
 // The mixed-precision pass adds per-row statistics and a queue of undecided
@@ -282,15 +288,21 @@ int pick_bucket(const Inst &I, const sng_config *cfg, void *workspace, size_t ws
     return SNG_OK;
 }
 
-// Pass (a) plus post-processing for one carved instance. norms: the per-row
-// statistics array of a similarity instance (computed first), else null.
+// Per-row arrays of a similarity instance (see launch_similarity_rows).
+struct SimRows {
+    float *nrm = nullptr;
+    float *unit = nullptr;
+};
+
+// Pass (a) plus post-processing for one carved instance. sim: the per-row
+// arrays of a similarity instance (written first), else null.
 int run_plain(Inst &I, const sng_config *cfg, bool labels_wanted, const BucketGeom *B,
-              hipStream_t st, float2 *norms = nullptr)
+              hipStream_t st, const SimRows *sim = nullptr)
 {
     // the plain layout keeps a stored partner-block sample valid
-    SNG_TRY(init_header(I.cnt, (uint64_t)I.n * I.m, I.band, st, norms == nullptr));
-    if (norms && I.m > 0)
-        SNG_TRY(launch_row_norms(I, norms, st));
+    SNG_TRY(init_header(I.cnt, (uint64_t)I.n * I.m, I.band, st, sim == nullptr));
+    if (sim && I.m > 0)
+        SNG_TRY(launch_similarity_rows(I, sim->nrm, sim->unit, st));
     SNG_TRY(launch_fill_u32(I.deg, I.n, 0u, st));
     if (I.m > 0 && B) {
         SNG_TRY(launch_fill_u32(I.mask, I.chunks * 8, 0u, st));
@@ -603,13 +615,15 @@ int sng_dbscan(const float *X, int64_t n, int32_t d, int64_t ld, double s, doubl
     return run_plain(I, cfg, true, use ? &B : nullptr, st);
 }
 
-int sng_similarity_workspace_size(int64_t n, int32_t d, int64_t m, int32_t flags, size_t *bytes)
+int sng_similarity_workspace_size(int64_t n, int32_t d, int64_t m, int32_t kind, int32_t flags,
+                                  size_t *bytes)
 {
-    if (!bytes || n < 0 || d < 1 || m < 0 || (flags & ~SNG_WS_DIRECT))
+    if (!bytes || n < 0 || d < 1 || m < 0 || (flags & ~SNG_WS_DIRECT) ||
+        (kind != SNG_SIM_DOT && kind != SNG_SIM_COSINE))
         return SNG_EINVAL;
     if (n > kMaxN || m > kMaxM)
         return SNG_ERANGE;
-    size_t b = sim_ws_bytes(n, m);
+    size_t b = sim_ws_bytes(n, d, m, kind);
     BucketGeom g;
     if (!(flags & SNG_WS_DIRECT) && bucket_geometry(n, d, m, true, &g))
         b = align_up(b + bucket_bytes(g));
@@ -632,7 +646,7 @@ int sng_dbscan_similarity(const float *X, int64_t n, int32_t d, int64_t ld, doub
     if ((rc = m_from_s(s, n, &m))) return rc;
     if (n > 0 && !labels) return SNG_EINVAL;
     if (n > 0 && (((uintptr_t)labels & 3u) || ((uintptr_t)degrees & 3u))) return SNG_EINVAL;
-    const size_t need = sim_ws_bytes(n, m);
+    const size_t need = sim_ws_bytes(n, d, m, kind);
     if (!workspace || ws_bytes < need) return SNG_EWORKSPACE;
     hipStream_t st = (hipStream_t)stream;
     Carve cv(workspace);
@@ -642,17 +656,19 @@ int sng_dbscan_similarity(const float *X, int64_t n, int32_t d, int64_t ld, doub
     uint32_t *wdeg = cv.take<uint32_t>((size_t)n);
     I.core = cv.take<uint8_t>((size_t)n);
     I.mask = cv.take<uint32_t>(sizes_for(n, m).chunks * 8);
-    float2 *norms = cv.take<float2>((size_t)n);
+    float *rows = cv.take<float>(sim_rows_floats(n, d, kind));
     I.deg = degrees ? degrees : wdeg;
     I.labels = labels;
-    set_similarity(I, kind, tau, norms);
+    SimRows sim;
+    (kind == SNG_SIM_COSINE ? sim.unit : sim.nrm) = rows;
+    set_similarity(I, kind, tau, sim.nrm, sim.unit);
     sng_config tuned;
     cfg = effective_cfg(I, cfg, &tuned);
     BucketGeom B;
     bool use = false;
     if ((rc = pick_bucket(I, cfg, workspace, ws_bytes, cv.off, &B, &use, kLayoutSimilarity)))
         return rc;
-    return run_plain(I, cfg, true, use ? &B : nullptr, st, norms);
+    return run_plain(I, cfg, true, use ? &B : nullptr, st, &sim);
 }
 
 int sng_dbscan_lowp(const float *X, int64_t n, int32_t d, int64_t ld, const uint16_t *X_lp,

@@ -1,0 +1,25 @@
+// Partner-block evaluate kernels for the sweep (level codes and histograms).
+#include "sng_bucket_eval.hpp"
+
+namespace sng {
+
+hipError_t launch_bucket_eval_sweep(const Inst &I, const SweepArgs &S, const BucketGeom &B,
+                                    const PassAShape &sh, hipStream_t st)
+{
+    const bool vec_ok = ((uintptr_t)I.X % 16 == 0) && (I.ld % 4 == 0);
+    return dispatch(I.d, vec_ok, sh, [&]<class Row, int OB>(uint32_t) -> hipError_t {
+        if constexpr (Row::kPrefetch) {
+            if (use_buffer(I))
+                hipLaunchKernelGGL((k_bkt_eval_sweep<Row, OB, true>), dim3(eval_blocks(B)),
+                                   dim3(256), 0, st, I, B, S);
+            else
+                hipLaunchKernelGGL((k_bkt_eval_sweep<Row, OB, false>), dim3(eval_blocks(B)),
+                                   dim3(256), 0, st, I, B, S);
+            return hipGetLastError();
+        } else {
+            return hipErrorInvalidValue;
+        }
+    });
+}
+
+}  // namespace sng

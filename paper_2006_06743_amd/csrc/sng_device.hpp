@@ -29,34 +29,44 @@ enum Counter : int {
 // Similarity queries other than the distance: an edge when the dot product
 // (kSimDot) or the cosine (kSimCos) of the pair is at least tau; binary64 in
 // coordinate order decides, as for the distance. The binary32 pass still
-// computes the squared distance F: by polarisation <a,b> = (|a|^2 + |b|^2 -
-// |a-b|^2) / 2, so the dot product reaches t exactly when |a-b|^2 <= |a|^2 +
-// |b|^2 - 2t, a threshold of the pair (t = tau, or tau |a||b| for the cosine).
+// computes a squared distance F and filters with a band around a threshold:
 //
-// Band: with K = |a|^2 + |b|^2 + 2|t|, the binary32 F is within 2a*K + beta
-// of |a-b|^2 (a = gamma_{d+2} of binary32, |a-b|^2 <= 2K), the binary64 dot
-// product within gamma_d(binary64)*K/2 of the exact one, and the cosine's
-// quotient, product and square roots add relative errors of order d*2^-53.
-// The threshold is formed in binary32 from per-row norms rounded to binary32
-// (within 2^-23 relative), which costs a few binary32 units of K more. k
-// below is 2a + 2^-19 rounded up, which covers all of it with margin: F below
-// E - H is surely an edge, F above E + H surely not.
+// Cosine: the pass runs on a copy of the rows scaled to unit length, where
+// |u - v|^2 = 2 - 2 cos, so cos >= tau is the distance test against the
+// constant 2 - 2 tau; the band (lo, hi of the instance, set on the host)
+// also covers the rounding of the scaled copy.
+//
+// Dot product: by polarisation <a,b> = (|a|^2 + |b|^2 - |a-b|^2) / 2, so the
+// dot product reaches tau exactly when |a-b|^2 <= |a|^2 + |b|^2 - 2 tau, a
+// threshold of the pair. With K = |a|^2 + |b|^2 + 2|tau|, the binary32 F is
+// within 2a*K + beta of |a-b|^2 (a = gamma_{d+2} of binary32, |a-b|^2 <= 2K)
+// and the binary64 dot product within gamma_d(binary64)*K/2 of the exact
+// one; the threshold is formed in binary32 from per-row squared norms
+// rounded to binary32 (within 2^-23 relative), which costs a few binary32
+// units of K more. k = 2a + 2^-19 rounded up covers all of it with margin:
+// F below E - H is surely an edge, F above E + H surely not.
 enum : int32_t { kSimNone = 0, kSimDot = 1, kSimCos = 2 };
 
+// Per-row data a decision needs besides the two rows: nothing for the
+// distance and cosine queries, the nrm entry for the dot product.
+struct NoAux {};
+
 struct SimQuery {
-    const float2 *nrm;  // [n] per row {fl32 |x|^2, fl32 |x|}; NaN sends the row's pairs to binary64
+    const float *X0;    // the caller's rows, for the binary64 definition
+    int64_t ld0;        // their stride in floats
+    const float *nrm;   // dot product: [n] fl32 |x|^2 (NaN sends the row's pairs to binary64)
     int32_t kind;       // kSimNone: the distance query (the other fields unused)
-    float t;            // fl32(tau)
-    float k;            // relative half-width of the band (times K)
-    float beta;         // absolute half-width (flushed binary32 subnormals)
+    float t2;           // dot product: fl32(2 tau)
+    float k;            // dot product: relative half-width of the band (times K)
+    float beta;         // dot product: absolute half-width (flushed binary32 subnormals)
     double tau;         // the threshold of the binary64 definition
 
-    // 1: surely an edge, 0: surely not, -1: undecided (NaN operands included)
-    __device__ __forceinline__ int band(uint32_t i, uint32_t j, float F) const
+    // Dot-product band; na, nb: the two rows' nrm entries (loaded early by
+    // the caller, with the rows). 1: surely an edge, 0: surely not, -1:
+    // undecided (NaN operands included).
+    __device__ __forceinline__ int band(float na, float nb, float F) const
     {
-        const float2 a = nrm[i], b = nrm[j];
-        const float t2 = 2.0f * (kind == kSimCos ? t * (a.y * b.y) : t);
-        const float A = a.x + b.x;
+        const float A = na + nb;
         const float E = A - t2;
         const float H = k * (A + __builtin_fabsf(t2)) + beta;
         if (F <= E - H)

@@ -123,10 +123,14 @@ hipError_t launch_pass_a_batch(const Inst *table, int count, const uint64_t *chu
                                uint64_t total_chunks, int d, bool vec_ok, const PassAShape &sh,
                                hipStream_t st);
 
-// Similarity queries: fills I.sim for kind (kSimDot, kSimCos) and tau, with
-// nrm the caller-carved [n] array that launch_row_norms writes.
-void set_similarity(Inst &I, int32_t kind, double tau, float2 *nrm);
-hipError_t launch_row_norms(const Inst &I, float2 *nrm, hipStream_t st);
+// Similarity queries: set_similarity fills I.sim (and for the cosine the
+// band and the row pointer of the unit copy) for kind (kSimDot, kSimCos) and
+// tau; launch_similarity_rows then writes the per-row data the pass reads:
+// nrm [n] (dot product) or the unit copy [n][unit_copy_ld(d)] (cosine), both
+// carved by the caller.
+int64_t unit_copy_ld(int32_t d);
+void set_similarity(Inst &I, int32_t kind, double tau, float *nrm, float *unit);
+hipError_t launch_similarity_rows(const Inst &I, float *nrm, float *unit, hipStream_t st);
 
 // Post-processing kernels (core mask, hooks, finalize).
 hipError_t launch_fill_u32(uint32_t *p, uint64_t count, uint32_t v, hipStream_t st);

@@ -19,6 +19,8 @@
 // sum and the binary64 definition; a slot that falls inside the band is
 // re-decided with the defining binary64 sum, so every decision equals the
 // binary64 one.
+#include <type_traits>
+
 #include "sng_pass_a.hpp"
 
 namespace sng {
@@ -26,9 +28,10 @@ namespace sng {
 // Plain decision: accept iff the binary32 distance is surely below the band,
 // or the binary64 recheck accepts. Accepted slots add to both degrees and set
 // their accept bit (kept per call: four bits per lane, eight lanes per word).
-// kSim: the similarity query of the instance instead, through its per-pair
-// band on the same binary32 distance.
-template <bool kSim>
+// kQ: the query (kSimNone: the distance against eps; kSimCos: the same band
+// test on the unit-scaled copy, rechecked with the binary64 cosine of the
+// caller's rows; kSimDot: the per-pair band of SimQuery on the caller's rows).
+template <int kQ>
 struct PlainPolicy {
     uint32_t *deg;
     uint32_t *mask;
@@ -38,7 +41,17 @@ struct PlainPolicy {
     int out_deg = 0;     // 1: out-degrees (no partner-side count)
     uint32_t deg_i = 0;  // accepted slots of the cached source row
     uint32_t nib = 0;    // accept bits of this lane's own call
+    using Aux = std::conditional_t<kQ == kSimDot, float, NoAux>;
+    Aux src_aux{};       // the cached source row's nrm entry
 
+    __device__ __forceinline__ Aux aux(uint32_t j) const
+    {
+        if constexpr (kQ == kSimDot)
+            return sim.nrm[j];
+        else
+            return Aux{};
+    }
+    __device__ __forceinline__ void enter_source(uint32_t i) { src_aux = aux(i); }
     __device__ __forceinline__ void begin_chunk() { nib = 0; }
     __device__ __forceinline__ void flush_source(uint32_t src, int q)
     {
@@ -46,23 +59,26 @@ struct PlainPolicy {
             atomicAdd(deg + src, deg_i);
         deg_i = 0;
     }
-    __device__ __forceinline__ int decide(float F, uint32_t i, uint32_t j, const float *rowi,
-                                          const float *rowj, int d, Tally &t, int q)
+    __device__ __forceinline__ int decide(float F, uint32_t i, uint32_t j, Aux aj,
+                                          const float *rowi, const float *rowj, int d, Tally &t,
+                                          int q)
     {
-        if constexpr (kSim) {
-            const int r = sim.band(i, j, F);
+        if constexpr (kQ == kSimDot) {
+            const int r = sim.band(src_aux, aj, F);
             if (r >= 0)
                 return r;
-            t.rechecked += (q == 0);
-            return sim_accept_f64(rowi, rowj, d, sim.kind, sim.tau);
         } else {
             if (F <= lo)
                 return 1;
             if (F > hi)
                 return 0;
-            t.rechecked += (q == 0);
-            return sqdist_f64(rowi, rowj, d) <= eps2;
         }
+        t.rechecked += (q == 0);
+        if constexpr (kQ == kSimNone)
+            return sqdist_f64(rowi, rowj, d) <= eps2;
+        else
+            return sim_accept_f64(sim.X0 + (int64_t)i * sim.ld0, sim.X0 + (int64_t)j * sim.ld0, d,
+                                  kQ, sim.tau);
     }
     __device__ __forceinline__ void record(int acc, uint32_t, uint32_t j, int q, int o, int w,
                                            Tally &t)
@@ -88,10 +104,10 @@ struct PlainPolicy {
     }
 };
 
-template <bool kSim>
-__device__ __forceinline__ PlainPolicy<kSim> plain_policy(const Inst &I)
+template <int kQ>
+__device__ __forceinline__ PlainPolicy<kQ> plain_policy(const Inst &I)
 {
-    PlainPolicy<kSim> p;
+    PlainPolicy<kQ> p;
     p.deg = I.deg;
     p.mask = I.mask;
     p.lo = I.lo;
@@ -102,7 +118,7 @@ __device__ __forceinline__ PlainPolicy<kSim> plain_policy(const Inst &I)
     return p;
 }
 
-template <class Row, int OB, bool kSim>
+template <class Row, int OB, int kQ>
 __global__ __launch_bounds__(256) void k_pass_a(Inst I, uint32_t cpw, uint32_t slice_floats)
 {
     extern __shared__ float lds[];
@@ -110,7 +126,7 @@ __global__ __launch_bounds__(256) void k_pass_a(Inst I, uint32_t cpw, uint32_t s
     const uint64_t lo = wave * cpw;
     float *slice = lds + (threadIdx.x / kWave) * slice_floats;
     Tally t;
-    PlainPolicy<kSim> pol = plain_policy<kSim>(I);
+    PlainPolicy<kQ> pol = plain_policy<kQ>(I);
     if (lo < I.chunks)  // wave-uniform
         pass_a_range<Row, OB>(I, pol, lo, min(lo + cpw, I.chunks), slice, t);
     commit_tally(t, I.cnt);
@@ -144,7 +160,7 @@ __global__ __launch_bounds__(256) void k_pass_a_batch(const Inst *__restrict__ t
         const Inst I = table[a];
         const uint64_t end = min(hi, starts[a + 1]);
         Tally t;
-        PlainPolicy<false> pol = plain_policy<false>(I);
+        PlainPolicy<kSimNone> pol = plain_policy<kSimNone>(I);
         pass_a_range<Row, OB>(I, pol, lo - starts[a], end - starts[a], slice, t);
         commit_tally_wave(t, I.cnt);
         lo = end;
@@ -238,14 +254,14 @@ hipError_t go(const Inst &I, const PassAShape &sh, uint32_t slice, hipStream_t s
     if (blocks > 0x7FFFFFFFull)
         return hipErrorInvalidValue;
     const size_t lds = (size_t)slice * sizeof(float) * sh.waves_per_block;
-    if (I.sim.kind != kSimNone)
-        hipLaunchKernelGGL((k_pass_a<Row, OB, true>), dim3((unsigned)blocks),
-                           dim3(64 * sh.waves_per_block), lds, st, I, (uint32_t)sh.chunks_per_wave,
-                           slice);
+    const dim3 grid((unsigned)blocks), block(64 * sh.waves_per_block);
+    const uint32_t cpw = (uint32_t)sh.chunks_per_wave;
+    if (I.sim.kind == kSimDot)
+        hipLaunchKernelGGL((k_pass_a<Row, OB, kSimDot>), grid, block, lds, st, I, cpw, slice);
+    else if (I.sim.kind == kSimCos)
+        hipLaunchKernelGGL((k_pass_a<Row, OB, kSimCos>), grid, block, lds, st, I, cpw, slice);
     else
-        hipLaunchKernelGGL((k_pass_a<Row, OB, false>), dim3((unsigned)blocks),
-                           dim3(64 * sh.waves_per_block), lds, st, I, (uint32_t)sh.chunks_per_wave,
-                           slice);
+        hipLaunchKernelGGL((k_pass_a<Row, OB, kSimNone>), grid, block, lds, st, I, cpw, slice);
     return hipGetLastError();
 }
 

@@ -226,8 +226,10 @@ struct Tally {
 // partner rows are fetched first, then decided one after another. What a
 // decision is, and what it updates, is the policy's business (Pol):
 //   begin_chunk()                 per chunk, before any slot
+//   enter_source(src)             the group takes source row src
 //   flush_source(src, q)          the group leaves source row src
-//   decide(F, i, j, rowi, rowj, d, t, q)  group-uniform result for one slot
+//   aux(j) -> Aux                 per-row data of partner j, loaded with its row
+//   decide(F, i, j, aux_j, rowi, rowj, d, t, q)  group-uniform result for one slot
 //   record(r, i, j, q, o, w, t)   account one decided slot (call o, word w)
 //   end_chunk(global_chunk, lane) per chunk, after every slot
 // Every cross-lane operation happens under group-uniform control flow.
@@ -272,6 +274,7 @@ __device__ __forceinline__ void pass_a_range(const Inst &I, Pol &pol, uint64_t c
         for (int ob = 0; ob < kBatches; ++ob) {
             uint32_t io[OB], nv[OB], jj[OB][4];
             typename Row::Buf buf[OB][4];
+            typename Pol::Aux ax[OB][4];
 #pragma unroll
             for (int b = 0; b < OB; ++b) {
                 const int o = ob * OB + b;
@@ -290,6 +293,7 @@ __device__ __forceinline__ void pass_a_range(const Inst &I, Pol &pol, uint64_t c
                         const bool live = (uint32_t)w < nv[b] && jj[b][w] != io[b];
                         const uint32_t src = live ? jj[b][w] : 0u;  // row 0 always exists
                         buf[b][w] = Row::fetch(X + (int64_t)src * ld, q, d);
+                        ax[b][w] = pol.aux(src);
                     }
             }
 #pragma unroll
@@ -301,6 +305,7 @@ __device__ __forceinline__ void pass_a_range(const Inst &I, Pol &pol, uint64_t c
                     if (cached != 0xFFFFFFFFu)
                         pol.flush_source(cached, q);
                     xi.load(X + (int64_t)io[b] * ld, q, d, slice);
+                    pol.enter_source(io[b]);
                     cached = io[b];
                 }
 #pragma unroll
@@ -313,12 +318,14 @@ __device__ __forceinline__ void pass_a_range(const Inst &I, Pol &pol, uint64_t c
                         continue;
                     }
                     const float *rowj = X + (int64_t)jw * ld;
-                    if constexpr (!Row::kPrefetch)
+                    if constexpr (!Row::kPrefetch) {
                         buf[b][w] = Row::fetch(rowj, q, d);
+                        ax[b][w] = pol.aux(jw);
+                    }
                     float F = group_sum<G>(xi.partial(buf[b][w], q, d));
                     F = __int_as_float((int)group_bcast<G>((uint32_t)__float_as_int(F), 0));
-                    const int r =
-                        pol.decide(F, io[b], jw, X + (int64_t)io[b] * ld, rowj, d, tally, q);
+                    const int r = pol.decide(F, io[b], jw, ax[b][w], X + (int64_t)io[b] * ld,
+                                             rowj, d, tally, q);
                     pol.record(r, io[b], jw, q, o, w, tally);
                 }
             }
