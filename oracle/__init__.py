@@ -165,13 +165,20 @@ def slot_sqdist(X: np.ndarray, m: int, seed: int, i0: int = 0, i1: Optional[int]
     return out.reshape(i1 - i0, int(m))
 
 
+def _mode(exhaustive: bool, out_degree: bool, simple_graph: bool) -> int:
+    if exhaustive + out_degree + simple_graph > 1:
+        raise OracleError("exhaustive, out_degree and simple_graph exclude each other")
+    return 1 if exhaustive else (2 if out_degree else (3 if simple_graph else 0))
+
+
 def dbscan(X: np.ndarray, eps: float, min_pts: int, seed: int = 0, s: Optional[float] = None,
            m: Optional[int] = None, exhaustive: bool = False,
-           out_degree: bool = False) -> Result:
+           out_degree: bool = False, simple_graph: bool = False) -> Result:
     """SNG-DBSCAN (Algorithm 1). Give ``s`` (m = ceil(s*n)) or ``m``;
     ``exhaustive=True`` uses the full eps-neighbourhood graph instead;
     ``out_degree=True`` counts only a point's own accepted samples in its
-    degree (Lemma 2, Section 4.1)."""
+    degree (Lemma 2, Section 4.1); ``simple_graph=True`` counts distinct
+    accepted neighbours (each sampled pair once)."""
     X = _rows(X)
     n, d = X.shape
     if not exhaustive:
@@ -183,7 +190,7 @@ def dbscan(X: np.ndarray, eps: float, min_pts: int, seed: int = 0, s: Optional[f
     deg = np.zeros(n, np.uint32)
     st = np.zeros(8, np.uint64)
     _check(load().sng_oracle_dbscan(_ptr(X), n, d, d, int(m or 0), float(eps), int(min_pts),
-                                    int(seed), 1 if exhaustive else (2 if out_degree else 0),
+                                    int(seed), _mode(exhaustive, out_degree, simple_graph),
                                     _ptr(labels), _ptr(deg),
                                     _ptr(st)), "sng_oracle_dbscan")
     return _result(labels, deg, st)
@@ -191,7 +198,8 @@ def dbscan(X: np.ndarray, eps: float, min_pts: int, seed: int = 0, s: Optional[f
 
 def dbscan_similarity(X: np.ndarray, kind: int, tau: float, min_pts: int, seed: int = 0,
                       s: Optional[float] = None, m: Optional[int] = None,
-                      exhaustive: bool = False, out_degree: bool = False) -> Result:
+                      exhaustive: bool = False, out_degree: bool = False,
+                      simple_graph: bool = False) -> Result:
     """SNG-DBSCAN with a similarity query instead of the distance (Section 1):
     an edge when the dot product (kind DOT) or the cosine (kind COSINE) of the
     pair is >= tau. Sampling, modes and post-processing as in ``dbscan``."""
@@ -206,7 +214,7 @@ def dbscan_similarity(X: np.ndarray, kind: int, tau: float, min_pts: int, seed: 
     st = np.zeros(8, np.uint64)
     _check(load().sng_oracle_dbscan_similarity(_ptr(X), n, d, d, int(m or 0), int(kind),
                                                float(tau), int(min_pts), int(seed),
-                                               1 if exhaustive else (2 if out_degree else 0),
+                                               _mode(exhaustive, out_degree, simple_graph),
                                                _ptr(labels), _ptr(deg), _ptr(st)),
            "sng_oracle_dbscan_similarity")
     return _result(labels, deg, st)

@@ -417,6 +417,37 @@ static int postprocess(int64_t n, const pairlist *A, const uint32_t *deg, int32_
     return 0;
 }
 
+/* Simple-graph degrees: each distinct pair {a, b} of the accepted list
+ * counts once for both endpoints, however many slots sampled it, in either
+ * direction (the graph G of Algorithm 1 read as a simple graph). */
+static int cmp_i64(const void *x, const void *y)
+{
+    const int64_t a = *(const int64_t *)x, b = *(const int64_t *)y;
+    return (a > b) - (a < b);
+}
+
+static int simple_degrees(int64_t n, const pairlist *A, uint32_t *deg)
+{
+    const int64_t k = A->len / 2;
+    int64_t *keys = (int64_t *)malloc((size_t)(k > 0 ? k : 1) * sizeof(int64_t));
+    if (!keys)
+        return -3;
+    for (int64_t e = 0; e < k; ++e) {
+        int64_t a = A->v[2 * e], b = A->v[2 * e + 1];
+        keys[e] = a < b ? a * n + b : b * n + a;
+    }
+    qsort(keys, (size_t)k, sizeof(int64_t), cmp_i64);
+    memset(deg, 0, (size_t)n * sizeof(uint32_t));
+    for (int64_t e = 0; e < k; ++e) {
+        if (e > 0 && keys[e] == keys[e - 1])
+            continue;
+        deg[keys[e] / n]++;
+        deg[keys[e] % n]++;
+    }
+    free(keys);
+    return 0;
+}
+
 /* The whole method for one similarity query (validated by the callers). */
 static int run_method(const float *X, int64_t n, int32_t d, int64_t ld, int64_t m,
                       const query *q, int32_t min_pts, uint64_t seed, int32_t mode,
@@ -433,9 +464,12 @@ static int run_method(const float *X, int64_t n, int32_t d, int64_t ld, int64_t 
     int rc = 0;
     if (mode != 1) {
         /* mode 2: a point's degree counts only its own accepted samples (the
-         * neighbour count of Lemma 2's proof); the graph is the same */
+         * neighbour count of Lemma 2's proof); the graph is the same. */
         if (n > 0)
-            rc = sample_graph(X, n, d, ld, m, q, seed, 0, n, dg, local, &A, mode == 0);
+            rc = sample_graph(X, n, d, ld, m, q, seed, 0, n, dg, local, &A, mode != 2);
+        /* mode 3: the degree of the simple graph instead of the multigraph */
+        if (rc == 0 && mode == 3)
+            rc = simple_degrees(n, &A, dg);
     } else {
         /* exhaustive: the full neighbourhood graph of classical DBSCAN */
         for (int64_t i = 0; i < n && rc == 0; ++i)
@@ -464,7 +498,7 @@ int sng_oracle_dbscan(const float *X, int64_t n, int32_t d, int64_t ld, int64_t 
                       double eps, int32_t min_pts, uint64_t seed, int32_t mode,
                       int32_t *labels, uint32_t *deg, uint64_t *stats)
 {
-    if (!valid_points(X, n, d, ld) || !valid_eps(eps) || mode < 0 || mode > 2 ||
+    if (!valid_points(X, n, d, ld) || !valid_eps(eps) || mode < 0 || mode > 3 ||
         (n > 0 && !labels) || (mode != 1 && m < 0))
         return -1;
     const query q = distance_query(eps);
@@ -476,7 +510,7 @@ int sng_oracle_dbscan_similarity(const float *X, int64_t n, int32_t d, int64_t l
                                  int32_t mode, int32_t *labels, uint32_t *deg, uint64_t *stats)
 {
     if (!valid_points(X, n, d, ld) || (kind != SNG_ORACLE_DOT && kind != SNG_ORACLE_COSINE) ||
-        isnan(tau) || isinf(tau) || mode < 0 || mode > 2 || (n > 0 && !labels) ||
+        isnan(tau) || isinf(tau) || mode < 0 || mode > 3 || (n > 0 && !labels) ||
         (mode != 1 && m < 0))
         return -1;
     const query q = {kind, 0.0, tau};

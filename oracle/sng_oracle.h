@@ -83,8 +83,10 @@ int sng_oracle_slot_sqdist(const float *X, int64_t n, int32_t d, int64_t ld, int
  * full DBSCAN on the same post-processing. mode 2: the sampled graph of mode
  * 0, but a point's degree (and so its core test) counts only its own
  * accepted samples (Lemma 2, Section 4.1, and its proof); components and
- * borders still use every accepted pair. labels[n] and deg[n] are written;
- * deg may be NULL. */
+ * borders still use every accepted pair. mode 3: the sampled graph of mode
+ * 0 read as a simple graph: a point's degree is its number of distinct
+ * accepted neighbours, a pair sampled several times (by either endpoint)
+ * counting once. labels[n] and deg[n] are written; deg may be NULL. */
 int sng_oracle_dbscan(const float *X, int64_t n, int32_t d, int64_t ld, int64_t m,
                       double eps, int32_t min_pts, uint64_t seed, int32_t mode,
                       int32_t *labels, uint32_t *deg, uint64_t *stats);
