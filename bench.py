@@ -10,7 +10,8 @@ kernel, the oracle's CPU rate on a bounded sample, and the plain-vs-mixed,
 plain-vs-sweep and sequential-vs-batched comparisons.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--schedule auto|direct]
-                    [--forms small,mixed,sweep,batch,lidar,recovery,similarity | --no-forms]
+                    [--forms small,mixed,sweep,batch,lidar,recovery,similarity,simple_graph
+                     | --no-forms]
                     [--no-cpu-baseline]
                     [--calibrate-copy]
 """
@@ -305,10 +306,30 @@ def form_similarity(sng, torch, wl, reps):
     return out
 
 
+def form_simple_graph(sng, torch, wl, reps):
+    """Simple-graph degrees (distinct accepted neighbours, through the hash
+    table of accepted pairs) against the multigraph degrees, on the dense
+    1e6 x 16 mixture (sigma = 0.25)."""
+    W = wl.mixture_16d(sigma=0.25)
+    X = torch.from_numpy(W.X).cuda()
+    out = {"workload": W.name, "slots": W.n * sng.samples_per_point(W.s, W.n)}
+    for name, cfg in [("multigraph", sng.Config()), ("simple_graph", sng.Config(simple_graph=1))]:
+        lab, deg, ws = sng.dbscan(X, W.s, W.eps, W.min_pts, W.seed, cfg=cfg)
+        out[name + "_ms"] = _cuda_ms(torch, lambda: sng.dbscan(
+            X, W.s, W.eps, W.min_pts, W.seed, cfg=cfg, labels=lab, degrees_out=deg, ws=ws), reps)
+        st = sng.stats(ws)
+        out[name + "_core"] = st.n_core
+        out["accepted"] = st.accepted
+        del lab, deg, ws
+        torch.cuda.empty_cache()
+    return out
+
+
 FORMS = {"mixed": ("mixed_precision", form_mixed), "sweep": ("sweep", form_sweep),
          "batch": ("batch", form_batch),
          "recovery": ("recovery", form_recovery), "small": ("small", form_small),
-         "lidar": ("lidar", form_lidar), "similarity": ("similarity", form_similarity)}
+         "lidar": ("lidar", form_lidar), "similarity": ("similarity", form_similarity),
+         "simple_graph": ("simple_graph", form_simple_graph)}
 
 
 def time_forms(sng, torch, wl, which, reps=3):
@@ -331,7 +352,8 @@ def main():
     ap.add_argument("--schedule", choices=["tuned", "auto", "direct"], default="tuned",
                     help="tuned: the autotuner's choice (timed before the run); auto: the "
                          "library's rule (partner blocks here); direct: direct gathers")
-    ap.add_argument("--forms", default="small,mixed,sweep,batch,lidar,recovery,similarity",
+    ap.add_argument("--forms",
+                    default="small,mixed,sweep,batch,lidar,recovery,similarity,simple_graph",
                     help="comma-separated subset of small, mixed, sweep, batch, lidar, "
                          "recovery")
     ap.add_argument("--no-forms", action="store_true")

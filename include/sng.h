@@ -87,6 +87,7 @@ typedef struct {
     int32_t schedule;        /* 0 auto, 1 direct gathers, 2 partner-block (L2 reuse) */
     int32_t reuse_sample;    /* 1: evaluate the sample sng_sample left in the workspace */
     int32_t out_degree;      /* 1: degree = a point's own accepted samples (see below) */
+    int32_t simple_graph;    /* 1: degree = distinct accepted neighbours (see below) */
 } sng_config;
 /* schedule: the partner-block form sorts the sample slots by partner block
  * before gathering, so rows narrower than a 128-byte line are reused from
@@ -113,9 +114,22 @@ typedef struct {
  * result. A config whose launch-shape fields are all zero still runs with
  * the tuned shape of sng_autotune. */
 
-/* Flag for sng_workspace_size: size for the direct schedule only (smaller;
- * a workspace of that size makes the automatic schedule choose it). */
+/* simple_graph (sng_degrees, sng_dbscan, sng_dbscan_similarity; SNG_EINVAL
+ * together with out_degree or reuse_sample, SNG_ENOTIMPL in the mixed form
+ * and the sweep): the sampled graph is read as a simple graph, so the degree
+ * of a point, and so its core test, counts its distinct accepted neighbours;
+ * a pair sampled several times, by either endpoint, counts once. Components
+ * and borders are unchanged. The accepted pairs go through a hash table in
+ * the workspace, sized for every slot accepted: 8 * 2^ceil(log2(max(64,
+ * 2*n*m))) more bytes (sng_workspace_size with SNG_WS_SIMPLE_GRAPH). Only
+ * the part the accepted pairs need is cleared and used. Stats still count
+ * accepted slots. */
+
+/* Flags for sng_workspace_size: size for the direct schedule only (smaller;
+ * a workspace of that size makes the automatic schedule choose it), and add
+ * the table of the simple_graph mode. */
 #define SNG_WS_DIRECT 0x100
+#define SNG_WS_SIMPLE_GRAPH 0x200
 
 /* Device-side counters, copied out by sng_stats_read. */
 typedef struct {
@@ -236,10 +250,10 @@ int sng_dbscan_lowp(const float *X, int64_t n, int32_t d, int64_t ld, const uint
  * a row whose squared norm lies outside [2^-100, 2^100], are decided by the
  * binary64 definition on the caller's rows, so results equal the definition
  * exactly. Workspace: sng_similarity_workspace_size for the same kind
- * (flags 0 or SNG_WS_DIRECT as for sng_workspace_size; the cosine adds
+ * (flags SNG_WS_DIRECT, SNG_WS_SIMPLE_GRAPH as for sng_workspace_size; the cosine adds
  * 4 * n * (d rounded up to a multiple of 4) bytes, the dot product 4 * n).
- * cfg: launch shape, schedule and out_degree as for sng_dbscan; reuse_sample
- * is not available (SNG_EINVAL). Stats: band_rel is the filter's half-width
+ * cfg: launch shape, schedule, out_degree and simple_graph as for
+ * sng_dbscan; reuse_sample is not available (SNG_EINVAL). Stats: band_rel is the filter's half-width
  * (cosine: absolute on |u - v|^2; dot product: relative to |x_i|^2 + |x_j|^2
  * + 2|tau|). */
 typedef enum {

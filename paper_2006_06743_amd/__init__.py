@@ -40,11 +40,12 @@ class Config:
     schedule: int = 0  # 0 auto, 1 direct gathers, 2 partner-block (L2 reuse)
     reuse_sample: int = 0  # 1: evaluate the sample that sample() left in the workspace
     out_degree: int = 0    # 1: a point's degree counts only its own accepted samples
+    simple_graph: int = 0  # 1: a point's degree counts its distinct accepted neighbours
 
     def c(self):
         return ctypes.byref(sng_config(self.lanes_per_pair, self.chunks_per_wave,
                                        self.stage_lds, self.prefetch, self.schedule,
-                                       self.reuse_sample, self.out_degree))
+                                       self.reuse_sample, self.out_degree, self.simple_graph))
 
 
 @dataclass
@@ -83,6 +84,11 @@ def _cfg(cfg: Optional[Config]):
     return cfg.c() if cfg is not None else None
 
 
+def _ws_flags(cfg: Optional[Config]) -> int:
+    """Workspace-size flags a configuration needs (the simple-graph table)."""
+    return _lib.SNG_WS_SIMPLE_GRAPH if cfg is not None and cfg.simple_graph else 0
+
+
 def samples_per_point(s: float, n: int) -> int:
     m = ctypes.c_int64()
     check(_lib.load().sng_samples_per_point(float(s), int(n), ctypes.byref(m)),
@@ -114,7 +120,7 @@ def degrees(X: torch.Tensor, m: int, eps: float, seed: int, cfg: Optional[Config
     if out is None:
         out = torch.empty(n, dtype=torch.int32, device=X.device)
     if ws is None:
-        ws = _ws(workspace_size(n, d, m), X.device)
+        ws = _ws(workspace_size(n, d, m, SNG_FP32 | _ws_flags(cfg)), X.device)
     check(_lib.load().sng_degrees(X.data_ptr(), n, d, ld, int(m), float(eps), int(seed),
                                   out.data_ptr(), ws.data_ptr(), ws.numel(), _cfg(cfg),
                                   _stream(X)), "sng_degrees")
@@ -193,7 +199,7 @@ def dbscan(X: torch.Tensor, s: float, eps: float, min_pts: int, seed: int,
     if want_degrees and degrees_out is None:
         degrees_out = torch.empty(n, dtype=torch.int32, device=X.device)
     if ws is None:
-        ws = _ws(workspace_size(n, d, m), X.device)
+        ws = _ws(workspace_size(n, d, m, SNG_FP32 | _ws_flags(cfg)), X.device)
     check(_lib.load().sng_dbscan(X.data_ptr(), n, d, ld, float(s), float(eps), int(min_pts),
                                  int(seed), labels.data_ptr(),
                                  degrees_out.data_ptr() if degrees_out is not None else None,
@@ -225,7 +231,7 @@ def dbscan_similarity(X: torch.Tensor, s: float, kind: int, tau: float, min_pts:
     if want_degrees and degrees_out is None:
         degrees_out = torch.empty(n, dtype=torch.int32, device=X.device)
     if ws is None:
-        ws = _ws(similarity_workspace_size(n, d, m, kind), X.device)
+        ws = _ws(similarity_workspace_size(n, d, m, kind, _ws_flags(cfg)), X.device)
     check(_lib.load().sng_dbscan_similarity(X.data_ptr(), n, d, ld, float(s), int(kind),
                                             float(tau), int(min_pts), int(seed),
                                             labels.data_ptr(),

@@ -15,6 +15,7 @@ SNG_OK, SNG_EINVAL, SNG_ERANGE, SNG_EWORKSPACE, SNG_EHIP, SNG_EOVERFLOW, SNG_ENO
     0, -1, -2, -3, -4, -5, -6
 SNG_FP32, SNG_BF16, SNG_FP16 = 0, 1, 2
 SNG_SIM_DOT, SNG_SIM_COSINE = 1, 2
+SNG_WS_DIRECT, SNG_WS_SIMPLE_GRAPH = 0x100, 0x200
 
 # Every symbol the header declares (checked by the CPU test suite).
 EXPORTS = [
@@ -33,7 +34,7 @@ class sng_config(ctypes.Structure):
     _fields_ = [("lanes_per_pair", ctypes.c_int32), ("chunks_per_wave", ctypes.c_int32),
                 ("stage_lds", ctypes.c_int32), ("prefetch", ctypes.c_int32),
                 ("schedule", ctypes.c_int32), ("reuse_sample", ctypes.c_int32),
-                ("out_degree", ctypes.c_int32)]
+                ("out_degree", ctypes.c_int32), ("simple_graph", ctypes.c_int32)]
 
 
 class sng_stats(ctypes.Structure):

@@ -88,6 +88,13 @@ size_t plain_ws_bytes(int64_t n, int64_t m)
     return b;
 }
 
+// The simple-graph degree mode adds the hash table of accepted pairs, sized
+// for every slot accepted (2^simple_table_log2 u64 entries).
+size_t simple_ws_bytes(int64_t n, int64_t m)
+{
+    return align_up(((size_t)1 << simple_table_log2(n, m)) * sizeof(unsigned long long));
+}
+
 // The similarity queries add per-row data: the binary32 squared norm (dot
 // product) or a unit-length copy of the row (cosine).
 size_t sim_rows_floats(int64_t n, int32_t d, int32_t kind)
@@ -177,6 +184,10 @@ int check_cfg(const sng_config *cfg)
         return SNG_EINVAL;  // a stored sample is evaluated by the partner-block schedule only
     if (cfg->out_degree != 0 && cfg->out_degree != 1)
         return SNG_EINVAL;
+    if (cfg->simple_graph != 0 && cfg->simple_graph != 1)
+        return SNG_EINVAL;
+    if (cfg->simple_graph && (cfg->out_degree || cfg->reuse_sample))
+        return SNG_EINVAL;  // one degree mode at a time; the table moves the sample
     return SNG_OK;
 }
 
@@ -234,7 +245,7 @@ TuneKey tune_key(const float *X, int32_t d, int64_t ld, int64_t n, int64_t m)
     return TuneKey{d, vec, ceil_log2((uint64_t)n), ceil_log2((uint64_t)m)};
 }
 
-// No launch shape chosen by the caller (out_degree is not a launch choice).
+// No launch shape chosen by the caller (the degree modes are not launch choices).
 bool is_default_cfg(const sng_config *cfg)
 {
     return !cfg || (cfg->lanes_per_pair == 0 && cfg->chunks_per_wave == 0 && cfg->stage_lds == 0 &&
@@ -257,6 +268,7 @@ const sng_config *effective_cfg(const Inst &I, const sng_config *cfg, sng_config
     if (buf->schedule == 2)
         buf->schedule = kPreferPartner;
     buf->out_degree = cfg ? cfg->out_degree : 0;
+    buf->simple_graph = cfg ? cfg->simple_graph : 0;
     return buf;
 }
 
@@ -294,13 +306,32 @@ struct SimRows {
     float *unit = nullptr;
 };
 
-// Pass (a) plus post-processing for one carved instance. sim: the per-row
-// arrays of a similarity instance (written first), else null.
-int run_plain(Inst &I, const sng_config *cfg, bool labels_wanted, const BucketGeom *B,
-              hipStream_t st, const SimRows *sim = nullptr)
+// The simple-graph table of a call, null when the mode is off.
+struct SimpleTable {
+    unsigned long long *table = nullptr;
+    uint32_t max_log2 = 0;
+};
+
+// Carves the simple-graph table when cfg asks for the mode.
+SimpleTable carve_simple(Carve &cv, const sng_config *cfg, int64_t n, int64_t m)
 {
-    // the plain layout keeps a stored partner-block sample valid
-    SNG_TRY(init_header(I.cnt, (uint64_t)I.n * I.m, I.band, st, sim == nullptr));
+    SimpleTable s;
+    if (cfg && cfg->simple_graph) {
+        s.max_log2 = simple_table_log2(n, m);
+        s.table = cv.take<unsigned long long>((size_t)1 << s.max_log2);
+    }
+    return s;
+}
+
+// Pass (a) plus post-processing for one carved instance. sim: the per-row
+// arrays of a similarity instance (written first), else null. simple: the
+// table of the simple-graph degree mode (table null: multigraph degrees).
+int run_plain(Inst &I, const sng_config *cfg, bool labels_wanted, const BucketGeom *B,
+              hipStream_t st, const SimRows *sim = nullptr, const SimpleTable &simple = {})
+{
+    // only the plain layout keeps a stored partner-block sample valid
+    SNG_TRY(init_header(I.cnt, (uint64_t)I.n * I.m, I.band, st,
+                        sim == nullptr && simple.table == nullptr));
     if (sim && I.m > 0)
         SNG_TRY(launch_similarity_rows(I, sim->nrm, sim->unit, st));
     SNG_TRY(launch_fill_u32(I.deg, I.n, 0u, st));
@@ -311,6 +342,9 @@ int run_plain(Inst &I, const sng_config *cfg, bool labels_wanted, const BucketGe
     } else if (I.m > 0) {
         SNG_TRY(launch_pass_a(I, shape_for(I, cfg), st));
     }
+    if (simple.table)
+        SNG_TRY(launch_simple_degrees(I, simple.table, simple.max_log2,
+                                      reinterpret_cast<uint32_t *>(I.cnt + kSimpleHdr), st));
     if (!labels_wanted)
         return SNG_OK;
     SNG_TRY(launch_core_init(I, st));
@@ -352,14 +386,17 @@ int sng_workspace_size(int64_t n, int32_t d, int64_t m, int32_t prec, size_t *by
     if (n > kMaxN || m > kMaxM)
         return SNG_ERANGE;
     const bool direct_only = (prec & SNG_WS_DIRECT) != 0;
-    prec &= ~SNG_WS_DIRECT;
+    const bool simple = (prec & SNG_WS_SIMPLE_GRAPH) != 0;
+    prec &= ~(SNG_WS_DIRECT | SNG_WS_SIMPLE_GRAPH);
     if (prec != SNG_FP32 && prec != SNG_BF16 && prec != SNG_FP16)
         return SNG_EINVAL;
     if (prec != SNG_FP32) {
+        if (simple)
+            return SNG_EINVAL;  // the mixed form has no simple-graph mode
         *bytes = lowp_ws_bytes(n, m);
         return SNG_OK;
     }
-    size_t b = plain_ws_bytes(n, m);
+    size_t b = plain_ws_bytes(n, m) + (simple ? simple_ws_bytes(n, m) : 0);
     BucketGeom g;
     if (!direct_only && bucket_geometry(n, d, m, true, &g))
         b = align_up(b + bucket_bytes(g));
@@ -378,7 +415,8 @@ int sng_degrees(const float *X, int64_t n, int32_t d, int64_t ld, int64_t m, dou
     if (m < 0) return SNG_EINVAL;
     if (m > kMaxM) return SNG_ERANGE;
     if (n > 0 && !degrees) return SNG_EINVAL;
-    const size_t need = plain_ws_bytes(n, m);
+    const size_t need =
+        plain_ws_bytes(n, m) + (cfg && cfg->simple_graph ? simple_ws_bytes(n, m) : 0);
     if (!workspace || ws_bytes < need) return SNG_EWORKSPACE;
     hipStream_t st = (hipStream_t)stream;
     Carve cv(workspace);
@@ -388,14 +426,16 @@ int sng_degrees(const float *X, int64_t n, int32_t d, int64_t ld, int64_t m, dou
     (void)cv.take<uint32_t>((size_t)n);
     I.core = cv.take<uint8_t>((size_t)n);
     I.mask = cv.take<uint32_t>(sizes_for(n, m).chunks * 8);
+    const SimpleTable simple = carve_simple(cv, cfg, n, m);
     I.deg = degrees;
     I.labels = nullptr;
     sng_config tuned;
     cfg = effective_cfg(I, cfg, &tuned);
     BucketGeom B;
     bool use = false;
-    if ((rc = pick_bucket(I, cfg, workspace, ws_bytes, cv.off, &B, &use))) return rc;
-    return run_plain(I, cfg, false, use ? &B : nullptr, st);
+    const uint32_t layout = simple.table ? kLayoutPlain | kLayoutSimpleTable : kLayoutPlain;
+    if ((rc = pick_bucket(I, cfg, workspace, ws_bytes, cv.off, &B, &use, layout))) return rc;
+    return run_plain(I, cfg, false, use ? &B : nullptr, st, nullptr, simple);
 }
 
 int sng_sample(int64_t n, int32_t d, int64_t m, uint64_t seed, void *workspace, size_t ws_bytes,
@@ -595,7 +635,8 @@ int sng_dbscan(const float *X, int64_t n, int32_t d, int64_t ld, double s, doubl
     if ((rc = m_from_s(s, n, &m))) return rc;
     if (n > 0 && !labels) return SNG_EINVAL;
     if (n > 0 && (((uintptr_t)labels & 3u) || ((uintptr_t)degrees & 3u))) return SNG_EINVAL;
-    const size_t need = plain_ws_bytes(n, m);
+    const size_t need =
+        plain_ws_bytes(n, m) + (cfg && cfg->simple_graph ? simple_ws_bytes(n, m) : 0);
     if (!workspace || ws_bytes < need) return SNG_EWORKSPACE;
     hipStream_t st = (hipStream_t)stream;
     Carve cv(workspace);
@@ -605,25 +646,28 @@ int sng_dbscan(const float *X, int64_t n, int32_t d, int64_t ld, double s, doubl
     uint32_t *wdeg = cv.take<uint32_t>((size_t)n);
     I.core = cv.take<uint8_t>((size_t)n);
     I.mask = cv.take<uint32_t>(sizes_for(n, m).chunks * 8);
+    const SimpleTable simple = carve_simple(cv, cfg, n, m);
     I.deg = degrees ? degrees : wdeg;
     I.labels = labels;
     sng_config tuned;
     cfg = effective_cfg(I, cfg, &tuned);
     BucketGeom B;
     bool use = false;
-    if ((rc = pick_bucket(I, cfg, workspace, ws_bytes, cv.off, &B, &use))) return rc;
-    return run_plain(I, cfg, true, use ? &B : nullptr, st);
+    const uint32_t layout = simple.table ? kLayoutPlain | kLayoutSimpleTable : kLayoutPlain;
+    if ((rc = pick_bucket(I, cfg, workspace, ws_bytes, cv.off, &B, &use, layout))) return rc;
+    return run_plain(I, cfg, true, use ? &B : nullptr, st, nullptr, simple);
 }
 
 int sng_similarity_workspace_size(int64_t n, int32_t d, int64_t m, int32_t kind, int32_t flags,
                                   size_t *bytes)
 {
-    if (!bytes || n < 0 || d < 1 || m < 0 || (flags & ~SNG_WS_DIRECT) ||
+    if (!bytes || n < 0 || d < 1 || m < 0 || (flags & ~(SNG_WS_DIRECT | SNG_WS_SIMPLE_GRAPH)) ||
         (kind != SNG_SIM_DOT && kind != SNG_SIM_COSINE))
         return SNG_EINVAL;
     if (n > kMaxN || m > kMaxM)
         return SNG_ERANGE;
-    size_t b = sim_ws_bytes(n, d, m, kind);
+    size_t b = sim_ws_bytes(n, d, m, kind) +
+               ((flags & SNG_WS_SIMPLE_GRAPH) ? simple_ws_bytes(n, m) : 0);
     BucketGeom g;
     if (!(flags & SNG_WS_DIRECT) && bucket_geometry(n, d, m, true, &g))
         b = align_up(b + bucket_bytes(g));
@@ -646,7 +690,8 @@ int sng_dbscan_similarity(const float *X, int64_t n, int32_t d, int64_t ld, doub
     if ((rc = m_from_s(s, n, &m))) return rc;
     if (n > 0 && !labels) return SNG_EINVAL;
     if (n > 0 && (((uintptr_t)labels & 3u) || ((uintptr_t)degrees & 3u))) return SNG_EINVAL;
-    const size_t need = sim_ws_bytes(n, d, m, kind);
+    const size_t need =
+        sim_ws_bytes(n, d, m, kind) + (cfg && cfg->simple_graph ? simple_ws_bytes(n, m) : 0);
     if (!workspace || ws_bytes < need) return SNG_EWORKSPACE;
     hipStream_t st = (hipStream_t)stream;
     Carve cv(workspace);
@@ -657,6 +702,7 @@ int sng_dbscan_similarity(const float *X, int64_t n, int32_t d, int64_t ld, doub
     I.core = cv.take<uint8_t>((size_t)n);
     I.mask = cv.take<uint32_t>(sizes_for(n, m).chunks * 8);
     float *rows = cv.take<float>(sim_rows_floats(n, d, kind));
+    const SimpleTable simple = carve_simple(cv, cfg, n, m);
     I.deg = degrees ? degrees : wdeg;
     I.labels = labels;
     SimRows sim;
@@ -666,9 +712,10 @@ int sng_dbscan_similarity(const float *X, int64_t n, int32_t d, int64_t ld, doub
     cfg = effective_cfg(I, cfg, &tuned);
     BucketGeom B;
     bool use = false;
-    if ((rc = pick_bucket(I, cfg, workspace, ws_bytes, cv.off, &B, &use, kLayoutSimilarity)))
-        return rc;
-    return run_plain(I, cfg, true, use ? &B : nullptr, st, &sim);
+    const uint32_t layout =
+        simple.table ? kLayoutSimilarity | kLayoutSimpleTable : kLayoutSimilarity;
+    if ((rc = pick_bucket(I, cfg, workspace, ws_bytes, cv.off, &B, &use, layout))) return rc;
+    return run_plain(I, cfg, true, use ? &B : nullptr, st, &sim, simple);
 }
 
 int sng_dbscan_lowp(const float *X, int64_t n, int32_t d, int64_t ld, const uint16_t *X_lp,
@@ -681,6 +728,7 @@ int sng_dbscan_lowp(const float *X, int64_t n, int32_t d, int64_t ld, const uint
     int rc = check_points(X, n, d, ld);
     if (rc) return rc;
     if ((rc = check_cfg(cfg))) return rc;
+    if (cfg && cfg->simple_graph) return SNG_ENOTIMPL;
     if ((rc = check_eps(eps))) return rc;
     if (prec != SNG_BF16 && prec != SNG_FP16) return SNG_EINVAL;
     if (!(lp_scale == lp_scale) || __builtin_isinf(lp_scale) || lp_scale == 0.0f) return SNG_EINVAL;
@@ -833,6 +881,7 @@ int sng_dbscan_sweep(const float *X, int64_t n, int32_t d, int64_t ld, double s,
     int rc = check_points(X, n, d, ld);
     if (rc) return rc;
     if ((rc = check_cfg(cfg))) return rc;
+    if (cfg && cfg->simple_graph) return SNG_ENOTIMPL;
     if (cfg && cfg->reuse_sample) return SNG_EINVAL;  // its workspace layout differs
     if (!eps || !min_pts || n_eps < 1 || n_minpts < 1) return SNG_EINVAL;
     if (n_eps > kSweepMaxK || n_minpts > kSweepMaxP) return SNG_ERANGE;

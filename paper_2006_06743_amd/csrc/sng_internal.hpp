@@ -95,11 +95,14 @@ struct BucketGeom {
 };
 // u64 index of BucketGeom::hdr inside an instance's counter header
 constexpr int kSampleHdr = 32;
+// u64 index of the simple-graph table's chosen log2 size in the header
+constexpr int kSimpleHdr = 40;
 // Workspace layouts whose record areas differ: a sample is valid only for
 // the layout that drew it.
 constexpr uint32_t kLayoutPlain = 1;
 constexpr uint32_t kLayoutSweep = 2;
 constexpr uint32_t kLayoutSimilarity = 3;
+constexpr uint32_t kLayoutSimpleTable = 0x10;  // or-ed in: a simple-graph table precedes the records
 uint64_t sample_tag(int64_t n, int64_t m, uint64_t seed, uint32_t bshift, uint32_t layout);
 bool bucket_geometry(int64_t n, int d, int64_t m, bool force, BucketGeom *g);
 size_t bucket_bytes(const BucketGeom &g);
@@ -131,6 +134,13 @@ hipError_t launch_pass_a_batch(const Inst *table, int count, const uint64_t *chu
 int64_t unit_copy_ld(int32_t d);
 void set_similarity(Inst &I, int32_t kind, double tau, float *nrm, float *unit);
 hipError_t launch_similarity_rows(const Inst &I, float *nrm, float *unit, hipStream_t st);
+
+// Simple-graph degrees (distinct accepted neighbours) from the accept bits
+// of the pass: table has 2^max_log2 u64 entries (simple_table_log2), the
+// size used is chosen on the device and kept in *log2_word.
+uint32_t simple_table_log2(int64_t n, int64_t m);
+hipError_t launch_simple_degrees(const Inst &I, unsigned long long *table, uint32_t max_log2,
+                                 uint32_t *log2_word, hipStream_t st);
 
 // Post-processing kernels (core mask, hooks, finalize).
 hipError_t launch_fill_u32(uint32_t *p, uint64_t count, uint32_t v, hipStream_t st);

@@ -171,3 +171,39 @@ def test_similarity_arguments_rejected_before_launch(lib):
     assert lib.sng_similarity_workspace_size(1000, 16, 50, 0, 0, ctypes.byref(b)) == -1
     assert lib.sng_similarity_workspace_size(-1, 16, 50, 1, 0, ctypes.byref(b)) == -1
     assert lib.sng_similarity_workspace_size(2**31, 16, 50, 2, 0, ctypes.byref(b)) == -2
+
+
+def test_simple_graph_config_and_workspace(lib):
+    from paper_2006_06743_amd._lib import sng_config
+    fake = ctypes.c_void_p(0x1000)
+    ws = ctypes.c_void_p(0x2000)
+    lab = ctypes.c_void_p(0x3000)
+    for fields in [(0, 0, 0, 0, 0, 0, 0, 2), (0, 0, 0, 0, 0, 0, 1, 1), (0, 0, 0, 0, 2, 1, 0, 1)]:
+        c = sng_config(*fields)
+        assert lib.sng_dbscan(fake, 10, 2, 2, 0.5, 1.0, 3, 1, lab, None, ws, 10**9,
+                              ctypes.byref(c), None) == -1, fields
+    simple = sng_config(0, 0, 0, 0, 0, 0, 0, 1)
+    # the mixed form and the sweep have no simple-graph mode
+    assert lib.sng_dbscan_lowp(fake, 10, 2, 2, fake, 8, 1.0, 1, 0.5, 1.0, 3, 1, lab, None, ws,
+                               10**9, ctypes.byref(simple), None) == -6
+    e = (ctypes.c_double * 1)(1.0)
+    mp = (ctypes.c_int32 * 1)(3)
+    assert lib.sng_dbscan_sweep(fake, 10, 2, 2, 0.5, e, 1, mp, 1, 1, lab, None, ws, 10**9,
+                                ctypes.byref(simple), None) == -6
+    # the table: 8 bytes per entry, 2^ceil(log2(max(64, 2 n m))) entries
+    b, c = ctypes.c_size_t(), ctypes.c_size_t()
+    for n, m in [(10, 2), (1000, 50), (12345, 77)]:
+        assert lib.sng_workspace_size(n, 3, m, 0x100, ctypes.byref(c)) == 0
+        assert lib.sng_workspace_size(n, 3, m, 0x300, ctypes.byref(b)) == 0
+        entries = 64
+        while entries < 2 * n * m:
+            entries *= 2
+        assert b.value - c.value == 8 * entries
+        assert lib.sng_similarity_workspace_size(n, 3, m, 1, 0x300, ctypes.byref(b)) == 0
+        assert lib.sng_similarity_workspace_size(n, 3, m, 1, 0x100, ctypes.byref(c)) == 0
+        assert b.value - c.value == 8 * entries
+    assert lib.sng_workspace_size(100, 3, 5, 1 | 0x200, ctypes.byref(b)) == -1  # mixed form
+    # too small for the table
+    assert lib.sng_workspace_size(1000, 3, 50, 0x100, ctypes.byref(c)) == 0
+    assert lib.sng_dbscan(fake, 1000, 3, 3, 0.05, 1.0, 3, 1, lab, None, ws, c.value,
+                          ctypes.byref(simple), None) == -3
