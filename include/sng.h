@@ -121,9 +121,9 @@ typedef struct {
  * a pair sampled several times, by either endpoint, counts once. Components
  * and borders are unchanged. The accepted pairs go through a hash table in
  * the workspace, sized for every slot accepted: 8 * 2^ceil(log2(max(64,
- * 2*n*m))) more bytes (sng_workspace_size with SNG_WS_SIMPLE_GRAPH). Only
- * the part the accepted pairs need is cleared and used. Stats still count
- * accepted slots. */
+ * 2*n*m))) more bytes (sng_workspace_size with SNG_WS_SIMPLE_GRAPH), and
+ * SNG_ERANGE when that exceeds 2^36 entries. Only the part the accepted
+ * pairs need is cleared and used. Stats still count accepted slots. */
 
 /* Flags for sng_workspace_size: size for the direct schedule only (smaller;
  * a workspace of that size makes the automatic schedule choose it), and add

@@ -89,10 +89,21 @@ size_t plain_ws_bytes(int64_t n, int64_t m)
 }
 
 // The simple-graph degree mode adds the hash table of accepted pairs, sized
-// for every slot accepted (2^simple_table_log2 u64 entries).
+// for every slot accepted (2^simple_table_log2 u64 entries), at most
+// 2^kSimpleMaxLog2 entries (512 GB, more than a GPU holds).
+constexpr uint32_t kSimpleMaxLog2 = 36;
+
 size_t simple_ws_bytes(int64_t n, int64_t m)
 {
     return align_up(((size_t)1 << simple_table_log2(n, m)) * sizeof(unsigned long long));
+}
+
+// SNG_ERANGE when the simple-graph table of (n, m) would exceed the cap.
+int check_simple(const sng_config *cfg, int64_t n, int64_t m)
+{
+    if (cfg && cfg->simple_graph && simple_table_log2(n, m) > kSimpleMaxLog2)
+        return SNG_ERANGE;
+    return SNG_OK;
 }
 
 // The similarity queries add per-row data: the binary32 squared norm (dot
@@ -396,6 +407,8 @@ int sng_workspace_size(int64_t n, int32_t d, int64_t m, int32_t prec, size_t *by
         *bytes = lowp_ws_bytes(n, m);
         return SNG_OK;
     }
+    if (simple && simple_table_log2(n, m) > kSimpleMaxLog2)
+        return SNG_ERANGE;
     size_t b = plain_ws_bytes(n, m) + (simple ? simple_ws_bytes(n, m) : 0);
     BucketGeom g;
     if (!direct_only && bucket_geometry(n, d, m, true, &g))
@@ -415,6 +428,7 @@ int sng_degrees(const float *X, int64_t n, int32_t d, int64_t ld, int64_t m, dou
     if (m < 0) return SNG_EINVAL;
     if (m > kMaxM) return SNG_ERANGE;
     if (n > 0 && !degrees) return SNG_EINVAL;
+    if ((rc = check_simple(cfg, n, m))) return rc;
     const size_t need =
         plain_ws_bytes(n, m) + (cfg && cfg->simple_graph ? simple_ws_bytes(n, m) : 0);
     if (!workspace || ws_bytes < need) return SNG_EWORKSPACE;
@@ -635,6 +649,7 @@ int sng_dbscan(const float *X, int64_t n, int32_t d, int64_t ld, double s, doubl
     if ((rc = m_from_s(s, n, &m))) return rc;
     if (n > 0 && !labels) return SNG_EINVAL;
     if (n > 0 && (((uintptr_t)labels & 3u) || ((uintptr_t)degrees & 3u))) return SNG_EINVAL;
+    if ((rc = check_simple(cfg, n, m))) return rc;
     const size_t need =
         plain_ws_bytes(n, m) + (cfg && cfg->simple_graph ? simple_ws_bytes(n, m) : 0);
     if (!workspace || ws_bytes < need) return SNG_EWORKSPACE;
@@ -666,6 +681,8 @@ int sng_similarity_workspace_size(int64_t n, int32_t d, int64_t m, int32_t kind,
         return SNG_EINVAL;
     if (n > kMaxN || m > kMaxM)
         return SNG_ERANGE;
+    if ((flags & SNG_WS_SIMPLE_GRAPH) && simple_table_log2(n, m) > kSimpleMaxLog2)
+        return SNG_ERANGE;
     size_t b = sim_ws_bytes(n, d, m, kind) +
                ((flags & SNG_WS_SIMPLE_GRAPH) ? simple_ws_bytes(n, m) : 0);
     BucketGeom g;
@@ -690,6 +707,7 @@ int sng_dbscan_similarity(const float *X, int64_t n, int32_t d, int64_t ld, doub
     if ((rc = m_from_s(s, n, &m))) return rc;
     if (n > 0 && !labels) return SNG_EINVAL;
     if (n > 0 && (((uintptr_t)labels & 3u) || ((uintptr_t)degrees & 3u))) return SNG_EINVAL;
+    if ((rc = check_simple(cfg, n, m))) return rc;
     const size_t need =
         sim_ws_bytes(n, d, m, kind) + (cfg && cfg->simple_graph ? simple_ws_bytes(n, m) : 0);
     if (!workspace || ws_bytes < need) return SNG_EWORKSPACE;

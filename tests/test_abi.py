@@ -203,6 +203,12 @@ def test_simple_graph_config_and_workspace(lib):
         assert lib.sng_similarity_workspace_size(n, 3, m, 1, 0x100, ctypes.byref(c)) == 0
         assert b.value - c.value == 8 * entries
     assert lib.sng_workspace_size(100, 3, 5, 1 | 0x200, ctypes.byref(b)) == -1  # mixed form
+    # the table is capped at 2^36 entries
+    assert lib.sng_workspace_size(2**30, 3, 2**5, 0x300, ctypes.byref(b)) == 0  # 2nm = 2^36
+    assert lib.sng_workspace_size(2**30, 3, 2**6, 0x300, ctypes.byref(b)) == -2
+    assert lib.sng_similarity_workspace_size(2**30, 3, 2**6, 2, 0x200, ctypes.byref(b)) == -2
+    assert lib.sng_dbscan(fake, 2**30, 3, 3, 2.0**-23, 1.0, 3, 1, lab, None, ws, 2**62,
+                          ctypes.byref(simple), None) == -2
     # too small for the table
     assert lib.sng_workspace_size(1000, 3, 50, 0x100, ctypes.byref(c)) == 0
     assert lib.sng_dbscan(fake, 1000, 3, 3, 0.05, 1.0, 3, 1, lab, None, ws, c.value,
