@@ -241,21 +241,22 @@ int sng_dbscan_lowp(const float *X, int64_t n, int32_t d, int64_t ld, const uint
  *                   and quotient; a zero row has no cosine and no edge.
  * Sampling, degrees, core points, components and borders are those of
  * sng_dbscan. tau: any finite value (SNG_EINVAL otherwise); kind: one of the
- * two above (SNG_EINVAL otherwise). The binary32 pass filters with a
- * squared distance: for the cosine on a unit-length copy of the rows (kept
- * in the workspace), where cos >= tau is |u - v|^2 <= 2 - 2 tau; for the dot
- * product on the rows themselves against the pair's threshold |x_i|^2 +
- * |x_j|^2 - 2 tau (polarisation), from squared norms kept in the workspace.
- * Pairs within the filter's error bound of the threshold, and every pair of
- * a row whose squared norm lies outside [2^-100, 2^100], are decided by the
- * binary64 definition on the caller's rows, so results equal the definition
- * exactly. Workspace: sng_similarity_workspace_size for the same kind
- * (flags SNG_WS_DIRECT, SNG_WS_SIMPLE_GRAPH as for sng_workspace_size; the cosine adds
- * 4 * n * (d rounded up to a multiple of 4) bytes, the dot product 4 * n).
+ * two above (SNG_EINVAL otherwise). The binary32 pass filters: the cosine
+ * with the squared distance of a unit-length copy of the rows (kept in the
+ * workspace), where cos >= tau is |u - v|^2 <= 2 - 2 tau (a row whose
+ * squared norm lies outside [2^-100, 2^100] has NaN in the copy); the dot
+ * product with the binary32 dot product and the sum of absolute products,
+ * which bounds its rounding error. Pairs within the filter's error bound of
+ * the threshold, NaN and overflow included, are decided by the binary64
+ * definition on the caller's rows, so results equal the definition exactly.
+ * Workspace: sng_similarity_workspace_size for the same kind (flags
+ * SNG_WS_DIRECT, SNG_WS_SIMPLE_GRAPH as for sng_workspace_size; the cosine
+ * adds 4 * n * (d rounded up to a multiple of 4) bytes, the dot product
+ * nothing).
  * cfg: launch shape, schedule, out_degree and simple_graph as for
  * sng_dbscan; reuse_sample is not available (SNG_EINVAL). Stats: band_rel is the filter's half-width
- * (cosine: absolute on |u - v|^2; dot product: relative to |x_i|^2 + |x_j|^2
- * + 2|tau|). */
+ * (cosine: absolute on |u - v|^2; dot product: relative to the sum of
+ * absolute products). */
 typedef enum {
     SNG_SIM_DOT = 1,
     SNG_SIM_COSINE = 2

@@ -106,11 +106,11 @@ int check_simple(const sng_config *cfg, int64_t n, int64_t m)
     return SNG_OK;
 }
 
-// The similarity queries add per-row data: the binary32 squared norm (dot
-// product) or a unit-length copy of the row (cosine).
+// The cosine query adds a unit-length copy of the rows; the dot product
+// nothing.
 size_t sim_rows_floats(int64_t n, int32_t d, int32_t kind)
 {
-    return (size_t)n * (kind == SNG_SIM_COSINE ? (size_t)unit_copy_ld(d) : 1u);
+    return kind == SNG_SIM_COSINE ? (size_t)n * (size_t)unit_copy_ld(d) : 0u;
 }
 
 size_t sim_ws_bytes(int64_t n, int32_t d, int64_t m, int32_t kind)
@@ -311,10 +311,9 @@ int pick_bucket(const Inst &I, const sng_config *cfg, void *workspace, size_t ws
     return SNG_OK;
 }
 
-// Per-row arrays of a similarity instance (see launch_similarity_rows).
+// Per-row data of a similarity instance (see launch_similarity_rows).
 struct SimRows {
-    float *nrm = nullptr;
-    float *unit = nullptr;
+    float *unit = nullptr;  // cosine: unit-length copy of the rows
 };
 
 // The simple-graph table of a call, null when the mode is off.
@@ -344,7 +343,7 @@ int run_plain(Inst &I, const sng_config *cfg, bool labels_wanted, const BucketGe
     SNG_TRY(init_header(I.cnt, (uint64_t)I.n * I.m, I.band, st,
                         sim == nullptr && simple.table == nullptr));
     if (sim && I.m > 0)
-        SNG_TRY(launch_similarity_rows(I, sim->nrm, sim->unit, st));
+        SNG_TRY(launch_similarity_rows(I, sim->unit, st));
     SNG_TRY(launch_fill_u32(I.deg, I.n, 0u, st));
     if (I.m > 0 && B) {
         SNG_TRY(launch_fill_u32(I.mask, I.chunks * 8, 0u, st));
@@ -724,8 +723,8 @@ int sng_dbscan_similarity(const float *X, int64_t n, int32_t d, int64_t ld, doub
     I.deg = degrees ? degrees : wdeg;
     I.labels = labels;
     SimRows sim;
-    (kind == SNG_SIM_COSINE ? sim.unit : sim.nrm) = rows;
-    set_similarity(I, kind, tau, sim.nrm, sim.unit);
+    sim.unit = rows;
+    set_similarity(I, kind, tau, sim.unit);
     sng_config tuned;
     cfg = effective_cfg(I, cfg, &tuned);
     BucketGeom B;

@@ -4,8 +4,6 @@
 // compile in parallel).
 #pragma once
 
-#include <type_traits>
-
 #include "sng_pass_a.hpp"
 
 namespace sng {
@@ -16,9 +14,10 @@ constexpr uint32_t kRecOffShift = 18;  // record: call offset (14 bits) | word (
 // formed only inside the band. record() receives the slot's global call
 // number as a functor, evaluated only for accepted slots. kQ: the query, as
 // for the direct pass (kSimCos evaluates the unit-scaled copy in X and
-// rechecks the caller's rows; kSimDot uses the per-pair band).
+// rechecks the caller's rows; kSimDot uses the dot-product filter).
 template <int kQ>
 struct BucketPlainPolicy {
+    static constexpr bool kDot = kQ == kSimDot;
     int out_deg;  // 1: out-degrees (no partner-side count)
     const float *X;
     int64_t ld;
@@ -28,34 +27,29 @@ struct BucketPlainPolicy {
     float lo, hi;
     double eps2;
     SimQuery sim;
-    using Aux = std::conditional_t<kQ == kSimDot, float, NoAux>;
 
-    __device__ __forceinline__ Aux aux(uint32_t j) const
+    __device__ __forceinline__ int recheck(uint32_t i, uint32_t j, Tally &t, int q)
     {
-        if constexpr (kQ == kSimDot)
-            return sim.nrm[j];
-        else
-            return Aux{};
-    }
-    __device__ __forceinline__ int decide(float F, uint32_t i, uint32_t j, Aux ai, Aux aj,
-                                          Tally &t, int q)
-    {
-        if constexpr (kQ == kSimDot) {
-            const int r = sim.band(ai, aj, F);
-            if (r >= 0)
-                return r;
-        } else {
-            if (F <= lo)
-                return 1;
-            if (F > hi)
-                return 0;
-        }
         t.rechecked += (q == 0);
         if constexpr (kQ == kSimNone)
             return sqdist_f64(X + (int64_t)i * ld, X + (int64_t)j * ld, d) <= eps2;
         else
             return sim_accept_f64(sim.X0 + (int64_t)i * sim.ld0, sim.X0 + (int64_t)j * sim.ld0, d,
                                   kQ, sim.tau);
+    }
+    __device__ __forceinline__ int decide(float F, uint32_t i, uint32_t j, Tally &t, int q)
+    {
+        if (F <= lo)
+            return 1;
+        if (F > hi)
+            return 0;
+        return recheck(i, j, t, q);
+    }
+    __device__ __forceinline__ int decide_dot(float P, float Q, uint32_t i, uint32_t j, Tally &t,
+                                              int q)
+    {
+        const int r = sim.band_dot(P, Q);
+        return r >= 0 ? r : recheck(i, j, t, q);
     }
     template <class CallFn>
     __device__ __forceinline__ void record(int acc, uint32_t i, uint32_t j, CallFn call_of, int w,
@@ -84,11 +78,9 @@ struct BucketSweepPolicy {
     const double *e2;
     int K;
     float hi_max;
-    using Aux = NoAux;
+    static constexpr bool kDot = false;
 
-    __device__ __forceinline__ Aux aux(uint32_t) const { return Aux{}; }
-    __device__ __forceinline__ int decide(float F, uint32_t i, uint32_t j, Aux, Aux, Tally &t,
-                                          int q)
+    __device__ __forceinline__ int decide(float F, uint32_t i, uint32_t j, Tally &t, int q)
     {
         if (!(F <= hi_max))
             return K;
@@ -245,7 +237,6 @@ __device__ __forceinline__ void eval_ticket(const Inst &I, const BucketGeom &B, 
         uint32_t ii[P], cj[P];
         bool live[P];
         typename Row::Buf bi[P], bj[P];
-        typename Pol::Aux ai[P], aj[P];
 #pragma unroll
         for (int k = 0; k < P; ++k) {
             live[k] = f0 + (uint32_t)(k * kGroups + grp) < total;  // group-uniform
@@ -268,16 +259,21 @@ __device__ __forceinline__ void eval_ticket(const Inst &I, const BucketGeom &B, 
                 bj[k] = Row::fetch(X + (int64_t)sj * ld, q, d);
                 bi[k] = Row::fetch(X + (int64_t)si * ld, q, d);
             }
-            aj[k] = pol.aux(sj);
-            ai[k] = pol.aux(si);
         }
 #pragma unroll
         for (int k = 0; k < P; ++k) {
             if (!live[k])
                 continue;
-            float F = group_sum<G>(Row::partial2(bi[k], bj[k], q, d));
-            F = __int_as_float((int)group_bcast<G>((uint32_t)__float_as_int(F), 0));
-            const int res = pol.decide(F, ii[k], cj[k], ai[k], aj[k], tally, q);
+            int res;
+            if constexpr (Pol::kDot) {
+                const float2 pq = Row::partial2_dot(bi[k], bj[k], q, d);
+                const float P = group_all<G>(group_sum<G>(pq.x));
+                const float Q = group_all<G>(group_sum<G>(pq.y));
+                res = pol.decide_dot(P, Q, ii[k], cj[k], tally, q);
+            } else {
+                const float F = group_all<G>(group_sum<G>(Row::partial2(bi[k], bj[k], q, d)));
+                res = pol.decide(F, ii[k], cj[k], tally, q);
+            }
             const uint32_t vk = v[k], sk = sv[k];
             pol.record(res, ii[k], cj[k],
                        [&]() { return (r0 + sk) * kRangeCalls + (vk >> kRecOffShift); },

@@ -28,50 +28,40 @@ enum Counter : int {
 
 // Similarity queries other than the distance: an edge when the dot product
 // (kSimDot) or the cosine (kSimCos) of the pair is at least tau; binary64 in
-// coordinate order decides, as for the distance. The binary32 pass still
-// computes a squared distance F and filters with a band around a threshold:
+// coordinate order decides, as for the distance. The binary32 pass filters
+// and the definition decides inside the filter's error bound:
 //
-// Cosine: the pass runs on a copy of the rows scaled to unit length, where
-// |u - v|^2 = 2 - 2 cos, so cos >= tau is the distance test against the
-// constant 2 - 2 tau; the band (lo, hi of the instance, set on the host)
-// also covers the rounding of the scaled copy.
+// Cosine: the pass runs the distance kernels on a copy of the rows scaled to
+// unit length, where |u - v|^2 = 2 - 2 cos, so cos >= tau is the distance
+// test against the constant 2 - 2 tau; its band (the instance's lo, hi, set
+// on the host) also covers the rounding of the scaled copy.
 //
-// Dot product: by polarisation <a,b> = (|a|^2 + |b|^2 - |a-b|^2) / 2, so the
-// dot product reaches tau exactly when |a-b|^2 <= |a|^2 + |b|^2 - 2 tau, a
-// threshold of the pair. With K = |a|^2 + |b|^2 + 2|tau|, the binary32 F is
-// within 2a*K + beta of |a-b|^2 (a = gamma_{d+2} of binary32, |a-b|^2 <= 2K)
-// and the binary64 dot product within gamma_d(binary64)*K/2 of the exact
-// one; the threshold is formed in binary32 from per-row squared norms
-// rounded to binary32 (within 2^-23 relative), which costs a few binary32
-// units of K more. k = 2a + 2^-19 rounded up covers all of it with margin:
-// F below E - H is surely an edge, F above E + H surely not.
+// Dot product: the pass forms P = sum a_k b_k and Q = sum |a_k b_k| in
+// binary32 (any order, fused or not). |P - <a,b>| <= gamma_d (in binary32)
+// times sum |a_k b_k| <= gamma_d Q / (1 - gamma_d), plus flushed subnormals,
+// and the binary64 definition is within gamma_d (binary64) of the same sum;
+// so P above t + H surely reaches tau and P below t - H surely does not,
+// with H = k Q + c (k and c set on the host, c also covering the binary32
+// rounding of tau and of this arithmetic).
 enum : int32_t { kSimNone = 0, kSimDot = 1, kSimCos = 2 };
-
-// Per-row data a decision needs besides the two rows: nothing for the
-// distance and cosine queries, the nrm entry for the dot product.
-struct NoAux {};
 
 struct SimQuery {
     const float *X0;    // the caller's rows, for the binary64 definition
     int64_t ld0;        // their stride in floats
-    const float *nrm;   // dot product: [n] fl32 |x|^2 (NaN sends the row's pairs to binary64)
     int32_t kind;       // kSimNone: the distance query (the other fields unused)
-    float t2;           // dot product: fl32(2 tau)
-    float k;            // dot product: relative half-width of the band (times K)
-    float beta;         // dot product: absolute half-width (flushed binary32 subnormals)
+    float t;            // dot product: fl32(tau)
+    float k;            // dot product: relative half-width (times Q)
+    float c;            // dot product: absolute half-width
     double tau;         // the threshold of the binary64 definition
 
-    // Dot-product band; na, nb: the two rows' nrm entries (loaded early by
-    // the caller, with the rows). 1: surely an edge, 0: surely not, -1:
-    // undecided (NaN operands included).
-    __device__ __forceinline__ int band(float na, float nb, float F) const
+    // Dot-product decision from P and Q: 1 surely an edge, 0 surely not,
+    // -1 undecided (NaN or infinite operands included).
+    __device__ __forceinline__ int band_dot(float P, float Q) const
     {
-        const float A = na + nb;
-        const float E = A - t2;
-        const float H = k * (A + __builtin_fabsf(t2)) + beta;
-        if (F <= E - H)
+        const float H = k * Q + c;
+        if (P > t + H)
             return 1;
-        if (F > E + H)
+        if (P < t - H)
             return 0;
         return -1;
     }
@@ -294,6 +284,14 @@ __device__ __forceinline__ float group_sum(float v)
     if constexpr (G >= 2)
         v += dpp_f<0xB1>(v);   // quad_perm [1,0,3,2]
     return v;
+}
+
+// The group's first lane's value in every lane of the group: makes a value
+// that a reduction left equal across the group uniform to the compiler.
+template <int G>
+__device__ __forceinline__ float group_all(float v)
+{
+    return __int_as_float((int)group_bcast<G>((uint32_t)__float_as_int(v), 0));
 }
 
 // OR of a value over 8 consecutive lanes (lanes 8k..8k+7); all receive it.

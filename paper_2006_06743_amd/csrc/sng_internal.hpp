@@ -128,12 +128,12 @@ hipError_t launch_pass_a_batch(const Inst *table, int count, const uint64_t *chu
 
 // Similarity queries: set_similarity fills I.sim (and for the cosine the
 // band and the row pointer of the unit copy) for kind (kSimDot, kSimCos) and
-// tau; launch_similarity_rows then writes the per-row data the pass reads:
-// nrm [n] (dot product) or the unit copy [n][unit_copy_ld(d)] (cosine), both
-// carved by the caller.
+// tau; launch_similarity_rows then writes the unit copy [n][unit_copy_ld(d)]
+// that the cosine's pass reads (carved by the caller; nothing for the dot
+// product).
 int64_t unit_copy_ld(int32_t d);
-void set_similarity(Inst &I, int32_t kind, double tau, float *nrm, float *unit);
-hipError_t launch_similarity_rows(const Inst &I, float *nrm, float *unit, hipStream_t st);
+void set_similarity(Inst &I, int32_t kind, double tau, float *unit);
+hipError_t launch_similarity_rows(const Inst &I, float *unit, hipStream_t st);
 
 // Simple-graph degrees (distinct accepted neighbours) from the accept bits
 // of the pass: table has 2^max_log2 u64 entries (simple_table_log2), the

@@ -19,8 +19,6 @@
 // sum and the binary64 definition; a slot that falls inside the band is
 // re-decided with the defining binary64 sum, so every decision equals the
 // binary64 one.
-#include <type_traits>
-
 #include "sng_pass_a.hpp"
 
 namespace sng {
@@ -30,9 +28,10 @@ namespace sng {
 // their accept bit (kept per call: four bits per lane, eight lanes per word).
 // kQ: the query (kSimNone: the distance against eps; kSimCos: the same band
 // test on the unit-scaled copy, rechecked with the binary64 cosine of the
-// caller's rows; kSimDot: the per-pair band of SimQuery on the caller's rows).
+// caller's rows; kSimDot: the dot-product filter of SimQuery).
 template <int kQ>
 struct PlainPolicy {
+    static constexpr bool kDot = kQ == kSimDot;
     uint32_t *deg;
     uint32_t *mask;
     float lo, hi;
@@ -41,17 +40,7 @@ struct PlainPolicy {
     int out_deg = 0;     // 1: out-degrees (no partner-side count)
     uint32_t deg_i = 0;  // accepted slots of the cached source row
     uint32_t nib = 0;    // accept bits of this lane's own call
-    using Aux = std::conditional_t<kQ == kSimDot, float, NoAux>;
-    Aux src_aux{};       // the cached source row's nrm entry
 
-    __device__ __forceinline__ Aux aux(uint32_t j) const
-    {
-        if constexpr (kQ == kSimDot)
-            return sim.nrm[j];
-        else
-            return Aux{};
-    }
-    __device__ __forceinline__ void enter_source(uint32_t i) { src_aux = aux(i); }
     __device__ __forceinline__ void begin_chunk() { nib = 0; }
     __device__ __forceinline__ void flush_source(uint32_t src, int q)
     {
@@ -59,26 +48,31 @@ struct PlainPolicy {
             atomicAdd(deg + src, deg_i);
         deg_i = 0;
     }
-    __device__ __forceinline__ int decide(float F, uint32_t i, uint32_t j, Aux aj,
-                                          const float *rowi, const float *rowj, int d, Tally &t,
-                                          int q)
+    __device__ __forceinline__ int recheck(uint32_t i, uint32_t j, const float *rowi,
+                                           const float *rowj, int d, Tally &t, int q)
     {
-        if constexpr (kQ == kSimDot) {
-            const int r = sim.band(src_aux, aj, F);
-            if (r >= 0)
-                return r;
-        } else {
-            if (F <= lo)
-                return 1;
-            if (F > hi)
-                return 0;
-        }
         t.rechecked += (q == 0);
         if constexpr (kQ == kSimNone)
             return sqdist_f64(rowi, rowj, d) <= eps2;
         else
             return sim_accept_f64(sim.X0 + (int64_t)i * sim.ld0, sim.X0 + (int64_t)j * sim.ld0, d,
                                   kQ, sim.tau);
+    }
+    __device__ __forceinline__ int decide(float F, uint32_t i, uint32_t j, const float *rowi,
+                                          const float *rowj, int d, Tally &t, int q)
+    {
+        if (F <= lo)
+            return 1;
+        if (F > hi)
+            return 0;
+        return recheck(i, j, rowi, rowj, d, t, q);
+    }
+    __device__ __forceinline__ int decide_dot(float P, float Q, uint32_t i, uint32_t j,
+                                              const float *rowi, const float *rowj, int d,
+                                              Tally &t, int q)
+    {
+        const int r = sim.band_dot(P, Q);
+        return r >= 0 ? r : recheck(i, j, rowi, rowj, d, t, q);
     }
     __device__ __forceinline__ void record(int acc, uint32_t, uint32_t j, int q, int o, int w,
                                            Tally &t)

@@ -13,6 +13,15 @@ namespace sng {
 // ---------------------------------------------------------------------------
 
 // G = 1, compile-time dimension D <= 8, scalar loads (any row stride).
+// Dot-product query: acc.x += a*b and acc.y += |a*b| (the second bounds the
+// rounding error of the first). Coordinates a row does not have are zero in
+// both sums.
+__device__ __forceinline__ void dot_step(float2 &acc, float a, float b)
+{
+    acc.x = __builtin_fmaf(a, b, acc.x);
+    acc.y = __builtin_fmaf(__builtin_fabsf(a), __builtin_fabsf(b), acc.y);
+}
+
 template <int D>
 struct SmallRow {
     static constexpr int kG = 1;
@@ -65,6 +74,18 @@ struct SmallRow {
             const float e = a.v[k] - b.v[k];
             acc = __builtin_fmaf(e, e, acc);
         }
+        return acc;
+    }
+    __device__ __forceinline__ float2 partial_dot(const Buf &b, int, int) const
+    {
+        return partial2_dot(r, b, 0, D);
+    }
+    __device__ __forceinline__ static float2 partial2_dot(const Buf &a, const Buf &b, int, int)
+    {
+        float2 acc = {0.0f, 0.0f};
+#pragma unroll
+        for (int k = 0; k < D; ++k)
+            dot_step(acc, a.v[k], b.v[k]);
         return acc;
     }
 };
@@ -131,6 +152,26 @@ struct VecRow {
         }
         return acc;
     }
+    __device__ __forceinline__ float2 partial_dot(const Buf &b, int q, int d) const
+    {
+        return partial2_dot(r, b, q, d);
+    }
+    __device__ __forceinline__ static float2 partial2_dot(const Buf &a, const Buf &b, int q, int d)
+    {
+        float2 acc = {0.0f, 0.0f};
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            const int k = 4 * (v * G + q);
+            dot_step(acc, a.v[v].x, b.v[v].x);
+            if (FULL || k + 1 < d)
+                dot_step(acc, a.v[v].y, b.v[v].y);
+            if (FULL || k + 2 < d)
+                dot_step(acc, a.v[v].z, b.v[v].z);
+            if (FULL || k + 3 < d)
+                dot_step(acc, a.v[v].w, b.v[v].w);
+        }
+        return acc;
+    }
 };
 
 // G lanes, NS scalars per lane: lane q holds coordinates v*G + q. Any row
@@ -182,6 +223,18 @@ struct ScalarRow {
         }
         return acc;
     }
+    __device__ __forceinline__ float2 partial_dot(const Buf &b, int q, int d) const
+    {
+        return partial2_dot(r, b, q, d);
+    }
+    __device__ __forceinline__ static float2 partial2_dot(const Buf &a, const Buf &b, int, int)
+    {
+        float2 acc = {0.0f, 0.0f};
+#pragma unroll
+        for (int v = 0; v < NS; ++v)
+            dot_step(acc, a.v[v], b.v[v]);
+        return acc;
+    }
 };
 
 // G = 64: the source row is staged in this wave's LDS slice (any d that fits);
@@ -213,6 +266,13 @@ struct LdsRow {
         }
         return acc;
     }
+    __device__ __forceinline__ float2 partial_dot(const Buf &b, int q, int d) const
+    {
+        float2 acc = {0.0f, 0.0f};
+        for (int k = q; k < d; k += 64)
+            dot_step(acc, s[k], b.p[k]);
+        return acc;
+    }
 };
 
 // Per-lane tallies, summed into the workspace counters at the end.
@@ -226,10 +286,11 @@ struct Tally {
 // partner rows are fetched first, then decided one after another. What a
 // decision is, and what it updates, is the policy's business (Pol):
 //   begin_chunk()                 per chunk, before any slot
-//   enter_source(src)             the group takes source row src
 //   flush_source(src, q)          the group leaves source row src
-//   aux(j) -> Aux                 per-row data of partner j, loaded with its row
-//   decide(F, i, j, aux_j, rowi, rowj, d, t, q)  group-uniform result for one slot
+//   decide(F, i, j, rowi, rowj, d, t, q)  group-uniform result for one slot
+//                                 from its binary32 squared distance F, or
+//   decide_dot(P, Q, i, j, ...)   from its binary32 dot product P and sum of
+//                                 absolute products Q when Pol::kDot
 //   record(r, i, j, q, o, w, t)   account one decided slot (call o, word w)
 //   end_chunk(global_chunk, lane) per chunk, after every slot
 // Every cross-lane operation happens under group-uniform control flow.
@@ -274,7 +335,6 @@ __device__ __forceinline__ void pass_a_range(const Inst &I, Pol &pol, uint64_t c
         for (int ob = 0; ob < kBatches; ++ob) {
             uint32_t io[OB], nv[OB], jj[OB][4];
             typename Row::Buf buf[OB][4];
-            typename Pol::Aux ax[OB][4];
 #pragma unroll
             for (int b = 0; b < OB; ++b) {
                 const int o = ob * OB + b;
@@ -293,7 +353,6 @@ __device__ __forceinline__ void pass_a_range(const Inst &I, Pol &pol, uint64_t c
                         const bool live = (uint32_t)w < nv[b] && jj[b][w] != io[b];
                         const uint32_t src = live ? jj[b][w] : 0u;  // row 0 always exists
                         buf[b][w] = Row::fetch(X + (int64_t)src * ld, q, d);
-                        ax[b][w] = pol.aux(src);
                     }
             }
 #pragma unroll
@@ -305,7 +364,6 @@ __device__ __forceinline__ void pass_a_range(const Inst &I, Pol &pol, uint64_t c
                     if (cached != 0xFFFFFFFFu)
                         pol.flush_source(cached, q);
                     xi.load(X + (int64_t)io[b] * ld, q, d, slice);
-                    pol.enter_source(io[b]);
                     cached = io[b];
                 }
 #pragma unroll
@@ -318,14 +376,19 @@ __device__ __forceinline__ void pass_a_range(const Inst &I, Pol &pol, uint64_t c
                         continue;
                     }
                     const float *rowj = X + (int64_t)jw * ld;
-                    if constexpr (!Row::kPrefetch) {
+                    if constexpr (!Row::kPrefetch)
                         buf[b][w] = Row::fetch(rowj, q, d);
-                        ax[b][w] = pol.aux(jw);
+                    int r;
+                    if constexpr (Pol::kDot) {
+                        const float2 pq = xi.partial_dot(buf[b][w], q, d);
+                        const float P = group_all<G>(group_sum<G>(pq.x));
+                        const float Q = group_all<G>(group_sum<G>(pq.y));
+                        r = pol.decide_dot(P, Q, io[b], jw, X + (int64_t)io[b] * ld, rowj, d,
+                                           tally, q);
+                    } else {
+                        const float F = group_all<G>(group_sum<G>(xi.partial(buf[b][w], q, d)));
+                        r = pol.decide(F, io[b], jw, X + (int64_t)io[b] * ld, rowj, d, tally, q);
                     }
-                    float F = group_sum<G>(xi.partial(buf[b][w], q, d));
-                    F = __int_as_float((int)group_bcast<G>((uint32_t)__float_as_int(F), 0));
-                    const int r = pol.decide(F, io[b], jw, ax[b][w], X + (int64_t)io[b] * ld,
-                                             rowj, d, tally, q);
                     pol.record(r, io[b], jw, q, o, w, tally);
                 }
             }

@@ -32,12 +32,10 @@ struct SweepPolicy {
     float hi_max;
     uint32_t own = 0;  // codes of this lane's own call
 
-    using Aux = NoAux;
-    __device__ __forceinline__ Aux aux(uint32_t) const { return Aux{}; }
-    __device__ __forceinline__ void enter_source(uint32_t) {}
+    static constexpr bool kDot = false;
     __device__ __forceinline__ void begin_chunk() { own = 0x01010101u * (uint32_t)K; }
     __device__ __forceinline__ void flush_source(uint32_t, int) {}
-    __device__ __forceinline__ int decide(float F, uint32_t, uint32_t, Aux, const float *rowi,
+    __device__ __forceinline__ int decide(float F, uint32_t, uint32_t, const float *rowi,
                                           const float *rowj, int d, Tally &t, int q)
     {
         if (!(F <= hi_max))

@@ -159,12 +159,12 @@ def test_similarity_arguments_rejected_before_launch(lib):
     assert call(s=-1.0) == -1 and call(labels=None) == -1
     assert call(wsb=10) == -3
     assert call(cfg=ctypes.byref(sng_config(0, 0, 0, 0, 0, 1))) == -1  # reuse_sample
-    # workspace: the dot product adds a float per point, the cosine a unit
-    # copy of the rows (d rounded up to a multiple of 4)
+    # workspace: the dot product adds nothing, the cosine a unit copy of the
+    # rows (d rounded up to a multiple of 4)
     b, c = ctypes.c_size_t(), ctypes.c_size_t()
     assert lib.sng_workspace_size(1000, 18, 50, 0x100, ctypes.byref(c)) == 0
     assert lib.sng_similarity_workspace_size(1000, 18, 50, 1, 0x100, ctypes.byref(b)) == 0
-    assert c.value + 4 * 1000 <= b.value <= c.value + 4 * 1000 + 256
+    assert b.value == c.value
     assert lib.sng_similarity_workspace_size(1000, 18, 50, 2, 0x100, ctypes.byref(b)) == 0
     assert c.value + 4 * 1000 * 20 <= b.value <= c.value + 4 * 1000 * 20 + 256
     assert lib.sng_similarity_workspace_size(1000, 16, 50, 1, 1, ctypes.byref(b)) == -1
