@@ -77,10 +77,11 @@ __global__ __launch_bounds__(256) void k_core_init(Inst I)
     count_add(I.cnt, kCntCore, n_core);
 }
 
-// One thread per accept word (eight consecutive calls of the instance). This
-// beats listing the accepted slots of a block first (hook_round), also on
-// the 10k x 2 blobs where 6% of slots are accepted: unions into a few dense
-// clusters contend, and the list form runs more of them at once.
+// One thread per accept word (eight consecutive calls of the instance).
+// Measured on the 10k x 2 blobs (6% of slots accepted, 85 us): listing a
+// block's accepted slots first (hook_round) or giving each call its own lane
+// is slower, fewer blocks are proportionally slower, and starting each union
+// from the source's last root gains nothing.
 __device__ __forceinline__ void hook_word(const Inst &I, uint64_t w)
 {
     const uint32_t bits = I.mask[I.chunk0 * 8ull + w];
@@ -174,7 +175,7 @@ hipError_t launch_hook_mask(const Inst &I, hipStream_t st)
 {
     if (I.chunks == 0)
         return hipSuccess;
-hipLaunchKernelGGL(k_hook_mask, dim3(grid_for(I.chunks * 8ull, 256)), dim3(256), 0, st, I);
+    hipLaunchKernelGGL(k_hook_mask, dim3(grid_for(I.chunks * 8ull, 256)), dim3(256), 0, st, I);
     return hipGetLastError();
 }
 
