@@ -237,7 +237,7 @@ def form_small(sng, torch, wl, reps):
     t_call = _cuda_ms(torch, lambda: sng.dbscan(X, W.s, W.eps, W.min_pts, W.seed, labels=lab,
                                                 degrees_out=deg, ws=ws), r)
     # the call enqueues this many kernels (rocprofv3 kernel trace of one call)
-    launches = 7
+    launches = 5
     tiny = torch.zeros(1, device="cuda")
 
     def empty():

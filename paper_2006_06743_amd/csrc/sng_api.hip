@@ -214,6 +214,24 @@ __global__ void k_header(unsigned long long *cnt, unsigned long long slots, doub
         cnt[kSampleHdr + t] = 0ull;  // this layout holds no partner-block sample
 }
 
+// The header of init_header plus deg[0..n) = 0, in one launch.
+__global__ void k_init_call(unsigned long long *cnt, unsigned long long slots, double band,
+                            int keep_sample, uint32_t *deg, uint64_t n)
+{
+    if (blockIdx.x == 0) {
+        const int t = threadIdx.x;
+        if (t < kCntNum)
+            cnt[t] = (t == kCntSlots) ? slots : 0ull;
+        if (t == 0)
+            ((double *)(cnt + kCntNum))[0] = band;
+        if (!keep_sample && t < 2)
+            cnt[kSampleHdr + t] = 0ull;
+    }
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        deg[i] = 0u;
+}
+
 // Counters of a call. keep_sample: the call uses the plain layout, so a
 // partner-block sample stored by an earlier call stays valid; every other
 // layout overwrites the record area and clears the sample's tag.
@@ -340,11 +358,16 @@ int run_plain(Inst &I, const sng_config *cfg, bool labels_wanted, const BucketGe
               hipStream_t st, const SimRows *sim = nullptr, const SimpleTable &simple = {})
 {
     // only the plain layout keeps a stored partner-block sample valid
-    SNG_TRY(init_header(I.cnt, (uint64_t)I.n * I.m, I.band, st,
-                        sim == nullptr && simple.table == nullptr));
+    {
+        const uint64_t blocks = ((uint64_t)I.n + 255) / 256;
+        hipLaunchKernelGGL(k_init_call, dim3(blocks == 0 ? 1 : (blocks > 4096 ? 4096 : blocks)),
+                           dim3(256), 0, st, I.cnt, (unsigned long long)I.n * I.m, I.band,
+                           (sim == nullptr && simple.table == nullptr) ? 1 : 0, I.deg,
+                           (uint64_t)I.n);
+        SNG_TRY(hipGetLastError());
+    }
     if (sim && I.m > 0)
         SNG_TRY(launch_similarity_rows(I, sim->unit, st));
-    SNG_TRY(launch_fill_u32(I.deg, I.n, 0u, st));
     if (I.m > 0 && B) {
         SNG_TRY(launch_fill_u32(I.mask, I.chunks * 8, 0u, st));
         SNG_TRY(launch_bucket_plain(I, *B, shape_for(I, cfg, true),

@@ -132,37 +132,6 @@ __global__ __launch_bounds__(256) void k_edge_degrees(const int32_t *edges, int6
     }
 }
 
-// Core points: label = root of the component (its minimum index).
-__global__ __launch_bounds__(256) void k_compress(Inst I)
-{
-    uint32_t roots = 0;
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < I.n;
-         i += (uint64_t)gridDim.x * blockDim.x) {
-        if (I.core[i]) {
-            const int32_t r = uf_root(I.labels, (int32_t)i);
-            st_relaxed(I.labels + i, r);
-            roots += (r == (int32_t)i);
-        }
-    }
-    count_add(I.cnt, kCntClusters, roots);
-}
-
-// Non-core points: label of the smallest core neighbour, or noise.
-__global__ __launch_bounds__(256) void k_borders(Inst I)
-{
-    uint32_t noise = 0;
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < I.n;
-         i += (uint64_t)gridDim.x * blockDim.x) {
-        if (!I.core[i]) {
-            const int32_t b = I.labels[i];
-            const int32_t l = (b == kNoCore) ? -1 : I.labels[b];
-            I.labels[i] = l;
-            noise += (l == -1);
-        }
-    }
-    count_add(I.cnt, kCntNoise, noise);
-}
-
 hipError_t launch_core_init(const Inst &I, hipStream_t st)
 {
     if (I.n == 0)
@@ -198,15 +167,38 @@ hipError_t launch_edge_degrees(const int32_t *edges, int64_t n_edges, uint32_t *
     return hipGetLastError();
 }
 
+// Both finalize steps in one launch: a core point takes the root of its
+// component, a non-core point the root of its smallest core neighbour (or
+// -1). Core entries are rewritten with their roots while other threads walk
+// the forest; a rewrite only shortens a path to the same root, so every
+// read-only walk still ends there. A non-core entry is read and written only
+// by its own thread (core walks never pass through non-core points).
+__global__ __launch_bounds__(256) void k_finalize(Inst I)
+{
+    uint32_t roots = 0, noise = 0;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < I.n;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        if (I.core[i]) {
+            const int32_t r = uf_root(I.labels, (int32_t)i);
+            st_relaxed(I.labels + i, r);
+            roots += (r == (int32_t)i);
+        } else {
+            const int32_t b = I.labels[i];
+            const int32_t l = (b == kNoCore) ? -1 : uf_root(I.labels, b);
+            I.labels[i] = l;
+            noise += (l == -1);
+        }
+    }
+    const int slots[2] = {kCntClusters, kCntNoise};
+    const uint32_t v[2] = {roots, noise};
+    block_count_add<2>(I.cnt, slots, v);
+}
+
 hipError_t launch_finalize(const Inst &I, hipStream_t st)
 {
     if (I.n == 0)
         return hipSuccess;
-    hipLaunchKernelGGL(k_compress, dim3(grid_for(I.n, 256)), dim3(256), 0, st, I);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess)
-        return e;
-    hipLaunchKernelGGL(k_borders, dim3(grid_for(I.n, 256)), dim3(256), 0, st, I);
+    hipLaunchKernelGGL(k_finalize, dim3(grid_for(I.n, 256)), dim3(256), 0, st, I);
     return hipGetLastError();
 }
 
