@@ -363,7 +363,7 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py: this build runs on one GPU only; --gpus %d (WORLD_SIZE=%d) is not "
+        print("bench.py: the library runs on one GPU; --gpus %d (WORLD_SIZE=%d) is not "
               "supported" % (args.gpus, world), file=sys.stderr, flush=True)
         sys.exit(2)
 

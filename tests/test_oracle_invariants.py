@@ -1,5 +1,5 @@
 """Invariants of SNG-DBSCAN's output that hold for any input (Algorithm 1 and
-the readings fixed for this build), checked on random sampled instances.
+the readings the oracle fixes), checked on random sampled instances.
 Accepted pairs are rebuilt here from the oracle's sampler and query, so these
 tests pin the sampling step's bookkeeping (self-skip, symmetrised degree, the
 accepted list fed to post-processing) against the post-processing pinned by
