@@ -87,39 +87,32 @@ __global__ __launch_bounds__(256) void k_b_hook(const Inst *__restrict__ T, cons
         hook_round(I, w0, hi, list, &nlist);
 }
 
-__global__ __launch_bounds__(256) void k_b_compress(const Inst *__restrict__ T, const BatchGeom G)
+// Both finalize steps of the instance's point range in one launch, as in the
+// single-instance finalize: core points take their root, non-core points the
+// root of their smallest core neighbour (read-only walks, which the
+// concurrent root rewrites only shorten), or -1.
+__global__ __launch_bounds__(256) void k_b_finalize(const Inst *__restrict__ T, const BatchGeom G)
 {
     const int k = block_instance(G.pblk, G.count, blockIdx.x);
     const Inst &I = T[k];
     const uint64_t lo = (blockIdx.x - G.pblk[k]) * kPointsPerBlock;
     const uint64_t hi = umin64(lo + kPointsPerBlock, I.n);
-    uint32_t roots = 0;
+    uint32_t roots = 0, noise = 0;
     for (uint64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
         if (I.core[i]) {
             const int32_t r = uf_root(I.labels, (int32_t)i);
             st_relaxed(I.labels + i, r);
             roots += (r == (int32_t)i);
-        }
-    }
-    batch_count(I.cnt, kCntClusters, roots);
-}
-
-__global__ __launch_bounds__(256) void k_b_borders(const Inst *__restrict__ T, const BatchGeom G)
-{
-    const int k = block_instance(G.pblk, G.count, blockIdx.x);
-    const Inst &I = T[k];
-    const uint64_t lo = (blockIdx.x - G.pblk[k]) * kPointsPerBlock;
-    const uint64_t hi = umin64(lo + kPointsPerBlock, I.n);
-    uint32_t noise = 0;
-    for (uint64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
-        if (!I.core[i]) {
+        } else {
             const int32_t b = I.labels[i];
-            const int32_t l = (b == kNoCore) ? -1 : I.labels[b];
+            const int32_t l = (b == kNoCore) ? -1 : uf_root(I.labels, b);
             I.labels[i] = l;
             noise += (l == -1);
         }
     }
-    batch_count(I.cnt, kCntNoise, noise);
+    const int slots[2] = {kCntClusters, kCntNoise};
+    const uint32_t v[2] = {roots, noise};
+    block_count_add<2>(I.cnt, slots, v);
 }
 
 hipError_t launch_batch(const Inst *T, const BatchGeom &G, int d, bool vec_ok,
@@ -145,10 +138,7 @@ hipError_t launch_batch(const Inst *T, const BatchGeom &G, int d, bool vec_ok,
         if ((e = hipGetLastError()) != hipSuccess)
             return e;
     }
-    hipLaunchKernelGGL(k_b_compress, dim3(pb), dim3(256), 0, st, T, G);
-    if ((e = hipGetLastError()) != hipSuccess)
-        return e;
-    hipLaunchKernelGGL(k_b_borders, dim3(pb), dim3(256), 0, st, T, G);
+    hipLaunchKernelGGL(k_b_finalize, dim3(pb), dim3(256), 0, st, T, G);
     return hipGetLastError();
 }
 
