@@ -427,3 +427,42 @@ def test_out_degree_mode(sng, orc, schedule):
         ref = orc.dbscan(X, eps, mp, seed, s=s, out_degree=True)
         assert_same(gl, gd, ref, "out-degree case %d" % case)
         assert st.accepted == ref.accepted and int(gd.sum()) == ref.accepted
+
+
+def test_concurrent_calls_on_two_streams(sng, orc):
+    """The library keeps no per-call global state: two host threads, each
+    with its own stream and workspace, run different instances at once."""
+    import threading
+    import torch
+    rng = np.random.default_rng(4321)
+    cases = []
+    for k in range(2):
+        X = wl.random_instance(rng, 20000, 3 + k, "blobs", spread=0.03)
+        cases.append((X, 0.02, 0.06 + 0.02 * k, 4, 11 + k))
+    refs = [orc.dbscan(X, eps, mp, seed, s=s) for X, s, eps, mp, seed in cases]
+    errors = []
+
+    def worker(idx):
+        try:
+            X, s, eps, mp, seed = cases[idx]
+            stream = torch.cuda.Stream()
+            with torch.cuda.stream(stream):
+                Xg = torch.from_numpy(X).cuda()
+                lab, deg, ws = sng.dbscan(Xg, s, eps, mp, seed)
+                for _ in range(5):
+                    sng.dbscan(Xg, s, eps, mp, seed, labels=lab, degrees_out=deg, ws=ws)
+                stream.synchronize()
+                got_l = lab.cpu().numpy()
+                got_d = deg.cpu().numpy().view(np.uint32)
+            if not (np.array_equal(got_l, refs[idx].labels) and
+                    np.array_equal(got_d, refs[idx].deg)):
+                errors.append("instance %d differs from the oracle" % idx)
+        except Exception as e:  # reported below
+            errors.append("instance %d: %r" % (idx, e))
+
+    threads = [threading.Thread(target=worker, args=(k,)) for k in range(2)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join(120)
+    assert not errors, errors
