@@ -21,9 +21,12 @@
  *            Euclidean distance evaluated in binary64: acc = 0; for k < d in
  *            order: delta = (double)x_ik - (double)x_jk; acc += delta*delta,
  *            every operation rounded to nearest-even, no fused multiply-add.
- *            NaN never forms an edge.
+ *            NaN never forms an edge. (sng_dbscan_similarity: a dot-product
+ *            or cosine threshold instead, defined there.)
  *   degree   symmetrised multigraph degree: each accepted sample adds one to
- *            both endpoints (a pair sampled twice counts twice).
+ *            both endpoints (a pair sampled twice counts twice); the
+ *            out_degree and simple_graph fields of sng_config select the
+ *            out-degree or the number of distinct neighbours instead.
  *   core     (int64)degree >= MinPts (MinPts <= 0 makes every point core).
  *   label    core point: smallest index of its core component;
  *            non-core point: label of its smallest-index core neighbour;
