@@ -202,8 +202,9 @@ int check_cfg(const sng_config *cfg)
     return SNG_OK;
 }
 
-__global__ void k_header(unsigned long long *cnt, unsigned long long slots, double band,
-                         int keep_sample)
+// The counters of a call (threads 0..kCntNum-1 of one block).
+__device__ __forceinline__ void write_header(unsigned long long *cnt, unsigned long long slots,
+                                             double band, int keep_sample)
 {
     const int t = threadIdx.x;
     if (t < kCntNum)
@@ -214,19 +215,18 @@ __global__ void k_header(unsigned long long *cnt, unsigned long long slots, doub
         cnt[kSampleHdr + t] = 0ull;  // this layout holds no partner-block sample
 }
 
+__global__ void k_header(unsigned long long *cnt, unsigned long long slots, double band,
+                         int keep_sample)
+{
+    write_header(cnt, slots, band, keep_sample);
+}
+
 // The header of init_header plus deg[0..n) = 0, in one launch.
 __global__ void k_init_call(unsigned long long *cnt, unsigned long long slots, double band,
                             int keep_sample, uint32_t *deg, uint64_t n)
 {
-    if (blockIdx.x == 0) {
-        const int t = threadIdx.x;
-        if (t < kCntNum)
-            cnt[t] = (t == kCntSlots) ? slots : 0ull;
-        if (t == 0)
-            ((double *)(cnt + kCntNum))[0] = band;
-        if (!keep_sample && t < 2)
-            cnt[kSampleHdr + t] = 0ull;
-    }
+    if (blockIdx.x == 0)
+        write_header(cnt, slots, band, keep_sample);
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (uint64_t)gridDim.x * blockDim.x)
         deg[i] = 0u;
