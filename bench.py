@@ -135,29 +135,36 @@ def _cuda_ms(torch, fn, reps):
 
 
 def form_mixed(sng, torch, wl, reps):
-    """Plain binary32 vs the bfloat16 MFMA form on the 784-d quantised images."""
+    """Plain binary32 vs the bfloat16 and float16 MFMA forms on the 784-d
+    quantised images (identical labels and degrees required)."""
+    import numpy as np
     W = wl.mnistlike_784d()
     X = torch.from_numpy(W.X).cuda()
-    Xlp = torch.from_numpy(W.X_lp.view(__import__("numpy").int16)).cuda()
     m = sng.samples_per_point(W.s, W.n)
     lab, deg, ws = sng.dbscan(X, W.s, W.eps, W.min_pts, W.seed)
     t_plain = _cuda_ms(torch, lambda: sng.dbscan(X, W.s, W.eps, W.min_pts, W.seed, labels=lab,
                                                  degrees_out=deg, ws=ws), reps)
     entry = {"workload": W.name, "slots": W.n * m, "plain_ms": t_plain}
-    try:
-        lab2, deg2, ws2 = sng.dbscan_lowp(X, Xlp, W.s, W.eps, W.min_pts, W.seed)
-        t_mixed = _cuda_ms(torch, lambda: sng.dbscan_lowp(X, Xlp, W.s, W.eps, W.min_pts,
-                                                          W.seed, ws=ws2), reps)
-        lab2, deg2, ws2 = sng.dbscan_lowp(X, Xlp, W.s, W.eps, W.min_pts, W.seed, ws=ws2)
-        torch.cuda.synchronize()
-        st = sng.stats(ws2)
-        entry.update({"mixed_bf16_ms": t_mixed, "speedup": t_plain / t_mixed,
-                      "labels_identical": bool(torch.equal(lab, lab2)),
-                      "degrees_identical": bool(torch.equal(deg, deg2)),
-                      "recheck_fraction": st.rechecked / max(1, st.slots),
-                      "band_rel": st.band_rel})
-    except sng.SNGError as e:
-        entry["mixed_bf16"] = "unavailable: %s" % e
+    copies = [("bf16", sng.SNG_BF16, W.X_lp), ("fp16", sng.SNG_FP16, wl.fp16_bits(W.X))]
+    for name, prec, bits in copies:
+        try:
+            Xlp = torch.from_numpy(bits.view(np.int16)).cuda()
+            lab2, deg2, ws2 = sng.dbscan_lowp(X, Xlp, W.s, W.eps, W.min_pts, W.seed, prec=prec)
+            t_mixed = _cuda_ms(torch, lambda: sng.dbscan_lowp(X, Xlp, W.s, W.eps, W.min_pts,
+                                                              W.seed, prec=prec, ws=ws2), reps)
+            lab2, deg2, ws2 = sng.dbscan_lowp(X, Xlp, W.s, W.eps, W.min_pts, W.seed, prec=prec,
+                                              ws=ws2)
+            torch.cuda.synchronize()
+            st = sng.stats(ws2)
+            key = "" if name == "bf16" else "_fp16"
+            entry.update({"mixed_%s_ms" % name: t_mixed, "speedup" + key: t_plain / t_mixed,
+                          "labels_identical" + key: bool(torch.equal(lab, lab2)),
+                          "degrees_identical" + key: bool(torch.equal(deg, deg2)),
+                          "recheck_fraction" + key: st.rechecked / max(1, st.slots),
+                          "band_rel" + key: st.band_rel})
+            del lab2, deg2, ws2, Xlp
+        except sng.SNGError as e:
+            entry["mixed_" + name] = "unavailable: %s" % e
     return entry
 
 
