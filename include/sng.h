@@ -42,7 +42,10 @@
  *     the next multiple of four floats when ld is a multiple of four).
  *   - `stream` is a hipStream_t passed as void* (NULL = default stream).
  *     Calls enqueue work on it and return without waiting; outputs are valid
- *     once the stream has been synchronised.
+ *     once the stream has been synchronised. sng_dbscan and
+ *     sng_dbscan_similarity enqueue kernels only (no memset, allocation or
+ *     host wait), so a call may be recorded into a HIP graph and replayed;
+ *     each replay recomputes every output from the inputs.
  *   - Arguments are validated before anything is enqueued; a call that
  *     returns a validation error has written nothing. SNG_EHIP reports a HIP
  *     call or launch that failed after earlier work was enqueued.

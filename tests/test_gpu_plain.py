@@ -466,3 +466,59 @@ def test_concurrent_calls_on_two_streams(sng, orc):
     for t in threads:
         t.join(120)
     assert not errors, errors
+
+
+@pytest.mark.parametrize("sched", [1, 2])
+def test_dbscan_in_a_captured_graph(sng, orc, sched):
+    """sng_dbscan enqueues kernels only (no memset, allocation or host wait),
+    so it can be captured into a HIP graph: three replays, with eager work
+    between them and the outputs overwritten each time, all equal the
+    oracle."""
+    import torch
+    W = wl.mixture_16d(sigma=0.25, n_total=100_000)
+    X = torch.from_numpy(W.X).cuda()
+    cfg = sng.Config(schedule=sched)
+    s = W.s * 20
+    lab, deg, ws = sng.dbscan(X, s, W.eps, W.min_pts, W.seed, cfg=cfg)
+    torch.cuda.synchronize()
+    ref = orc.dbscan(W.X, W.eps, W.min_pts, W.seed, s=s)
+    g = torch.cuda.CUDAGraph()
+    stream = torch.cuda.Stream()
+    stream.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.graph(g, stream=stream):
+        sng.dbscan(X, s, W.eps, W.min_pts, W.seed, cfg=cfg, labels=lab, degrees_out=deg, ws=ws)
+    junk = torch.zeros(1 << 20, device="cuda")
+    for rep in range(3):
+        lab.fill_(-7)
+        deg.fill_(12345)
+        junk += 1.0
+        g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(deg.cpu().numpy().view(np.uint32), ref.deg), "replay %d" % rep
+        assert np.array_equal(lab.cpu().numpy(), ref.labels), "replay %d" % rep
+    st = sng.stats(ws)
+    assert st.accepted == ref.accepted and st.n_clusters == ref.n_clusters
+
+
+def test_similarity_in_a_captured_graph(sng, orc):
+    """The cosine form (unit-copy pre-pass, then the same pass) captured and
+    replayed like sng_dbscan."""
+    import torch
+    rng = np.random.default_rng(91)
+    X = (wl.random_instance(rng, 30000, 8, "blobs", spread=0.05) - 0.5).astype(np.float32)
+    Xg = torch.from_numpy(X).cuda()
+    lab, deg, ws = sng.dbscan_similarity(Xg, 0.01, 2, 0.9, 4, 17)
+    torch.cuda.synchronize()
+    ref = orc.dbscan_similarity(X, 2, 0.9, 4, 17, s=0.01)
+    g = torch.cuda.CUDAGraph()
+    stream = torch.cuda.Stream()
+    stream.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.graph(g, stream=stream):
+        sng.dbscan_similarity(Xg, 0.01, 2, 0.9, 4, 17, labels=lab, degrees_out=deg, ws=ws)
+    for rep in range(3):
+        lab.fill_(-7)
+        deg.fill_(12345)
+        g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(deg.cpu().numpy().view(np.uint32), ref.deg), "replay %d" % rep
+        assert np.array_equal(lab.cpu().numpy(), ref.labels), "replay %d" % rep
