@@ -251,8 +251,15 @@ def form_small(sng, torch, wl, reps):
         for _ in range(launches):
             tiny.add_(0.0)
     t_floor = _cuda_ms(torch, empty, r)
+    # the same call recorded once into a HIP graph and replayed
+    g = torch.cuda.CUDAGraph()
+    stream = torch.cuda.Stream()
+    stream.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.graph(g, stream=stream):
+        sng.dbscan(X, W.s, W.eps, W.min_pts, W.seed, labels=lab, degrees_out=deg, ws=ws)
+    t_graph = _cuda_ms(torch, g.replay, r)
     return {"workload": W.name, "slots": W.n * sng.samples_per_point(W.s, W.n),
-            "call_us": t_call * 1e3, "launches": launches,
+            "call_us": t_call * 1e3, "graph_replay_us": t_graph * 1e3, "launches": launches,
             "empty_launches_us": t_floor * 1e3, "over_floor": t_call / t_floor}
 
 
