@@ -183,9 +183,12 @@ def test_recheck_band_adversarial(sng, orc):
 @pytest.mark.parametrize("schedule", [1, 2], ids=["direct", "partner_blocks"])
 def test_schedules_on_many_partner_blocks(sng, orc, schedule):
     """Both schedules on an instance spanning many partner blocks (d=3, so
-    blocks of 2^16 rows; n=300k gives five blocks) and on ragged sizes."""
+    blocks of 2^16 rows; n=300k gives five blocks) and on ragged sizes,
+    including both sides of n = 1024, where the partner draw switches from
+    a binary64 to a binary32 quotient estimate."""
     rng = np.random.default_rng(61)
     for n, d, s in [(300_001, 3, 0.0004), (70_000, 16, 0.003), (40_000, 32, 0.004),
+                    (1023, 2, 0.3), (1024, 3, 0.3), (1025, 2, 0.3),
                     (5, 2, 1.0), (1, 3, 2.0)]:
         X = wl.random_instance(rng, n, d, "blobs", spread=0.002)
         eps = 0.004 * np.sqrt(d)
