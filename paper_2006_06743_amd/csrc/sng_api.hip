@@ -153,6 +153,7 @@ Inst make_inst(const float *X, int64_t n, int32_t d, int64_t ld, int64_t m, doub
     I.key0 = (uint32_t)(seed & 0xFFFFFFFFull);
     I.key1 = (uint32_t)(seed >> 32);
     I.inv_n = n > 0 ? 1.0 / (double)n : 0.0;
+    I.inv_nf = (n >= 1024 && n <= ((int64_t)1 << 30)) ? (float)(1.0 / (double)n) : 0.0f;
     I.inv_C = z.C > 0 ? 1.0 / (double)z.C : 0.0;
     I.eps2 = eps * eps;
     band_fp32(I.eps2, d, &I.lo, &I.hi, &I.band);

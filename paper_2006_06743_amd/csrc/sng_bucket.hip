@@ -66,24 +66,8 @@ __device__ __forceinline__ uint32_t gen_exclusive(uint32_t v, uint32_t *wsum, ui
     return before + x - v;
 }
 
-// Exact w mod n for 1024 <= n <= 2^30 from a binary32 quotient estimate.
-// fl32(w), inv = fl32(fl64(1/n)) and their rounded product each carry a
-// relative error below 2^-24 (1 + 2^-28), so the estimate is within
-// (w/n) * 3.0001 * 2^-24 < 2^22 * 3.0001 * 2^-24 < 1 of w/n, and its
-// truncation q is one of floor(w/n) - 1, floor(w/n), floor(w/n) + 1. Then
-// w - q n lies in [-n, 2n), which 32-bit wrap-around holds exactly as n <=
-// 2^30, and of r, r + n and r - n exactly one lies in [0, n): the others are
-// at least n, or wrap to at least 2^32 - 2n >= 2^31. Their unsigned minimum
-// is the remainder.
-__device__ __forceinline__ uint32_t mod_f32(uint32_t w, uint32_t n, float inv)
-{
-    const uint32_t q = (uint32_t)((float)w * inv);
-    const uint32_t r = w - q * n;
-    return min(min(r, r + n), r - n);
-}
-
 template <bool kF32Mod>
-__global__ __launch_bounds__(kGenThreads) void k_bkt_generate(Inst I, BucketGeom B, float inv_nf)
+__global__ __launch_bounds__(kGenThreads) void k_bkt_generate(Inst I, BucketGeom B)
 {
     extern __shared__ uint32_t lds_u32[];
     __shared__ uint32_t wsum[kGenThreads / kWave];
@@ -122,7 +106,7 @@ __global__ __launch_bounds__(kGenThreads) void k_bkt_generate(Inst I, BucketGeom
         for (int w = 0; w < 4; ++w) {
             uint32_t kk = ~0u, rr = 0;
             if ((uint32_t)w < nvalid) {
-                const uint32_t j = kF32Mod ? mod_f32(W.w[w], I.n, inv_nf)
+                const uint32_t j = kF32Mod ? mod_f32(W.w[w], I.n, I.inv_nf)
                                            : mod_exact(W.w[w], I.n, I.inv_n);
                 if (j == ii) {
                     ++self;
@@ -248,12 +232,12 @@ hipError_t launch_bucket_generate(const Inst &I, const BucketGeom &B, hipStream_
         return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_bkt_prepare, dim3(1), dim3(64), 0, st, B, 1);
     const size_t lds = ((size_t)kRangeSlots + 2 * (size_t)B.NJ) * sizeof(uint32_t);
-    if (I.n >= 1024 && I.n <= (1u << 30))
+    if (I.inv_nf != 0.0f)
         hipLaunchKernelGGL(k_bkt_generate<true>, dim3((unsigned)B.ranges), dim3(kGenThreads), lds,
-                           st, I, B, (float)(1.0 / (double)I.n));
+                           st, I, B);
     else
         hipLaunchKernelGGL(k_bkt_generate<false>, dim3((unsigned)B.ranges), dim3(kGenThreads), lds,
-                           st, I, B, 0.0f);
+                           st, I, B);
     hipLaunchKernelGGL(k_bkt_seal, dim3(1), dim3(64), 0, st, B);
     return hipGetLastError();
 }

@@ -77,6 +77,7 @@ struct Inst {
     uint32_t C;             // Philox calls per point = ceil(m/4)
     uint32_t key0, key1;    // Philox key = seed
     double inv_n;           // fl64(1/n), for the exact remainder
+    float inv_nf;           // fl32(fl64(1/n)) when 1024 <= n <= 2^30, else 0
     double inv_C;           // fl64(1/C)
     float lo, hi;           // binary32 band: F <= lo accept, F > hi reject
     double eps2;            // fl64(eps*eps), the binary64 threshold
@@ -135,6 +136,37 @@ __device__ __forceinline__ uint32_t mod_exact(uint32_t w, uint32_t n, double inv
     r += (r < 0) ? (int64_t)n : 0;
     r -= (r >= (int64_t)n) ? (int64_t)n : 0;
     return (uint32_t)r;
+}
+
+// Exact w mod n for 1024 <= n <= 2^30 from a binary32 quotient estimate.
+// fl32(w), inv = fl32(fl64(1/n)) and their rounded product each carry a
+// relative error below 2^-24 (1 + 2^-28), so the estimate is within
+// (w/n) * 3.0001 * 2^-24 < 2^22 * 3.0001 * 2^-24 < 1 of w/n, and its
+// truncation q is one of floor(w/n) - 1, floor(w/n), floor(w/n) + 1. Then
+// w - q n lies in [-n, 2n), which 32-bit wrap-around holds exactly as n <=
+// 2^30, and of r, r + n and r - n exactly one lies in [0, n): the others are
+// at least n, or wrap to at least 2^32 - 2n >= 2^31. Their unsigned minimum
+// is the remainder.
+__device__ __forceinline__ uint32_t mod_f32(uint32_t w, uint32_t n, float inv)
+{
+    const uint32_t q = (uint32_t)((float)w * inv);
+    const uint32_t r = w - q * n;
+    return min(min(r, r + n), r - n);
+}
+
+// The four partners of one Philox call: its words mod n. The branch is
+// uniform (one instance per wavefront), so only one side runs.
+__device__ __forceinline__ void partners4(const Inst &I, const Words4 &W, uint32_t j[4])
+{
+    if (I.inv_nf != 0.0f) {
+#pragma unroll
+        for (int w = 0; w < 4; ++w)
+            j[w] = mod_f32(W.w[w], I.n, I.inv_nf);
+    } else {
+#pragma unroll
+        for (int w = 0; w < 4; ++w)
+            j[w] = mod_exact(W.w[w], I.n, I.inv_n);
+    }
 }
 
 // Exact floor division a / b for a < 2^40 and 1 <= b < 2^32: the binary64

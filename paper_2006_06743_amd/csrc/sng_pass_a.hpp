@@ -324,9 +324,7 @@ __device__ __forceinline__ void pass_a_range(const Inst &I, Pol &pol, uint64_t c
         const uint32_t nvalid = (ii < I.n) ? min(4u, I.m - 4u * cc) : 0u;
         const Words4 W = philox10(cc, ii, I.key0, I.key1);
         uint32_t j[4];
-#pragma unroll
-        for (int w = 0; w < 4; ++w)
-            j[w] = mod_exact(W.w[w], I.n, I.inv_n);
+        partners4(I, W, j);
 
         pol.begin_chunk();
         constexpr int kBatches = G / OB;
