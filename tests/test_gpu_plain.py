@@ -199,6 +199,29 @@ def test_schedules_on_many_partner_blocks(sng, orc, schedule):
 
 
 @pytest.mark.timeout(600)
+@pytest.mark.parametrize("n", [1 << 30, (1 << 30) + 1], ids=["n2p30", "n2p30_plus1"])
+def test_partner_draws_at_the_remainder_limit(sng, orc, n):
+    """n = 2^30 is the largest n whose partners come from the binary32
+    quotient estimate; n = 2^30 + 1 takes the binary64 one. With every point
+    equal (d = 1, m = 1) every slot is accepted, so deg[i] = (1 - self_i) +
+    in_i counts each source that drew i: every drawn partner index is
+    checked against the oracle's."""
+    import torch
+    m, eps, seed = 1, 1.0, 0x5EED2030
+    print("remainder limit n", n, flush=True)
+    X = torch.zeros((n, 1), dtype=torch.float32, device="cuda:0")
+    deg, ws = sng.degrees(X, m, eps, seed)
+    st = sng.stats(ws)
+    got = deg.cpu().numpy().view(np.uint32)
+    del deg, ws, X
+    torch.cuda.empty_cache()
+    ref, slots, self_pairs, accepted = orc.degrees(np.zeros((n, 1), np.float32), m, eps, seed)
+    assert slots == n and st.slots == n
+    assert st.self_pairs == self_pairs and st.accepted == accepted == n - self_pairs
+    assert np.array_equal(got, ref)
+
+
+@pytest.mark.timeout(600)
 @pytest.mark.parametrize("sigma", [1.0, 0.25])
 def test_mixture16d_full_size(sng, orc, sigma):
     """The n=1e6, d=16, s=0.001 workload (1e9 slots) at full size, plus the
