@@ -102,6 +102,13 @@ struct Words4 {
     uint32_t w[4];
 };
 
+// a ^ b ^ c in one instruction: gfx950's three-input bit operation with the
+// odd-parity truth table 0x96 (symmetric, so the operand order is free).
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c)
+{
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
 __device__ __forceinline__ Words4 philox10(uint32_t c, uint32_t i, uint32_t key0, uint32_t key1)
 {
     uint32_t x0 = c, x1 = i, x2 = 0u, x3 = 0u;
@@ -109,8 +116,8 @@ __device__ __forceinline__ Words4 philox10(uint32_t c, uint32_t i, uint32_t key0
     for (int r = 0; r < 10; ++r) {
         const uint64_t p = (uint64_t)0xD2511F53u * x0;  // multiplier 0
         const uint64_t q = (uint64_t)0xCD9E8D57u * x2;  // multiplier 1
-        const uint32_t y0 = (uint32_t)(q >> 32) ^ x1 ^ key0;
-        const uint32_t y2 = (uint32_t)(p >> 32) ^ x3 ^ key1;
+        const uint32_t y0 = xor3((uint32_t)(q >> 32), x1, key0);
+        const uint32_t y2 = xor3((uint32_t)(p >> 32), x3, key1);
         x1 = (uint32_t)q;
         x3 = (uint32_t)p;
         x0 = y0;
