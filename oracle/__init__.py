@@ -53,6 +53,8 @@ def load() -> ctypes.CDLL:
     lib.sng_oracle_dbscan_similarity.argtypes = [P, i64, i32, i64, i64, i32, dbl, i32, u64, i32,
                                                  P, P, P]
     lib.sng_oracle_dbscan_similarity.restype = ctypes.c_int
+    lib.sng_oracle_sweep.argtypes = [P, i64, i32, i64, i64, P, i32, P, i32, u64, i32, P, P, P]
+    lib.sng_oracle_sweep.restype = ctypes.c_int
     lib.sng_oracle_graph.argtypes = [i64, P, i64, i32, P, P, P]
     lib.sng_oracle_graph.restype = ctypes.c_int
     _lib = lib
@@ -232,19 +234,28 @@ def graph(n: int, edges, min_pts: int) -> Result:
 
 
 def sweep(X: np.ndarray, eps_grid, min_pts_grid, seed: int, s: Optional[float] = None,
-          m: Optional[int] = None):
-    """Every (eps, MinPts) pair of a grid, each solved by the single-instance
-    definition: labels [P][K][n], degrees [K][n]."""
-    K, P = len(eps_grid), len(min_pts_grid)
-    n = X.shape[0]
+          m: Optional[int] = None, out_degree: bool = False):
+    """Every (eps, MinPts) pair of a grid (Section 5 tunes eps over a grid),
+    each equal to ``dbscan(X, eps, MinPts, seed, ...)``: one sampling step at
+    the largest eps, then each grid point's edges taken from its accepted
+    pairs by the single run's own test. Returns labels [P][K][n], degrees
+    [K][n] and per-point stats [P][K][8]."""
+    X = _rows(X)
+    n, d = X.shape
+    if m is None:
+        m = samples_per_point(s, n)
+        if m < 0:
+            raise OracleError("invalid sampling rate")
+    e = np.ascontiguousarray(eps_grid, dtype=np.float64).ravel()
+    mp = np.ascontiguousarray(min_pts_grid, dtype=np.int32).ravel()
+    K, P = e.size, mp.size
     labels = np.empty((P, K, n), np.int32)
     degs = np.empty((K, n), np.uint32)
-    for k, e in enumerate(eps_grid):
-        for p, mp in enumerate(min_pts_grid):
-            r = dbscan(X, float(e), int(mp), seed, s=s, m=m)
-            labels[p, k] = r.labels
-            degs[k] = r.deg
-    return labels, degs
+    st = np.zeros((P, K, 8), np.uint64)
+    _check(load().sng_oracle_sweep(_ptr(X), n, d, d, int(m), _ptr(e), K, _ptr(mp), P,
+                                   int(seed), 2 if out_degree else 0, _ptr(labels), _ptr(degs),
+                                   _ptr(st)), "sng_oracle_sweep")
+    return labels, degs, st
 
 
 def compact_labels(labels) -> tuple[np.ndarray, int]:

@@ -517,6 +517,73 @@ int sng_oracle_dbscan_similarity(const float *X, int64_t n, int32_t d, int64_t l
     return run_method(X, n, d, ld, m, &q, min_pts, seed, mode, labels, deg, stats);
 }
 
+/* A grid of (eps, MinPts) pairs (Section 5 tunes eps over a grid of values),
+ * each solved as by sng_oracle_dbscan in mode 0 or 2. The sampling step runs
+ * once, at the largest eps of the grid, and keeps its accepted pairs; pair
+ * (i,j) is an edge at eps[k] iff D(i,j) <= fl64(eps[k]*eps[k]), the single
+ * run's own test, recomputed here per pair. Every edge at eps[k] is among
+ * the kept pairs because rounding eps*eps is monotone in eps. */
+int sng_oracle_sweep(const float *X, int64_t n, int32_t d, int64_t ld, int64_t m,
+                     const double *eps, int32_t n_eps, const int32_t *min_pts, int32_t n_minpts,
+                     uint64_t seed, int32_t mode, int32_t *labels, uint32_t *deg, uint64_t *stats)
+{
+    if (!valid_points(X, n, d, ld) || m < 0 || n_eps < 1 || n_minpts < 1 || !eps || !min_pts ||
+        (mode != 0 && mode != 2) || (n > 0 && !labels))
+        return -1;
+    double eps_max = 0.0;
+    for (int32_t k = 0; k < n_eps; ++k) {
+        if (!valid_eps(eps[k]))
+            return -1;
+        if (eps[k] > eps_max)
+            eps_max = eps[k];
+    }
+    if (m > 17179869184LL || (m > 0 && n > INT64_MAX / m))
+        return -2;
+    const size_t nn = (size_t)(n > 0 ? n : 1);
+    uint32_t *dg = (uint32_t *)calloc(nn, sizeof(uint32_t));
+    uint32_t *dk = (uint32_t *)malloc(nn * sizeof(uint32_t));
+    pairlist A = {0}, Ak = {0};
+    uint64_t base[8] = {0};
+    int rc = (dg && dk) ? 0 : -3;
+    const query qmax = distance_query(eps_max);
+    if (rc == 0 && n > 0)
+        rc = sample_graph(X, n, d, ld, m, &qmax, seed, 0, n, dg, base, &A, 1);
+    if (rc == 0) {
+        Ak.v = (int64_t *)malloc((size_t)(A.len > 0 ? A.len : 1) * sizeof(int64_t));
+        if (!Ak.v)
+            rc = -3;
+    }
+    for (int32_t k = 0; k < n_eps && rc == 0; ++k) {
+        const query q = distance_query(eps[k]);
+        Ak.len = 0;
+        memset(dk, 0, nn * sizeof(uint32_t));
+        for (int64_t e = 0; e < A.len; e += 2) {
+            const int64_t a = A.v[e], b = A.v[e + 1]; /* a is the sampling point */
+            if (!accepted(X, ld, d, a, b, &q))
+                continue;
+            Ak.v[Ak.len++] = a;
+            Ak.v[Ak.len++] = b;
+            dk[a]++;
+            if (mode != 2)
+                dk[b]++;
+        }
+        if (deg && n > 0)
+            memcpy(deg + (size_t)k * (size_t)n, dk, (size_t)n * sizeof(uint32_t));
+        for (int32_t p = 0; p < n_minpts && rc == 0; ++p) {
+            uint64_t local[8] = {base[0], base[1], (uint64_t)(Ak.len / 2), 0, 0, 0, 0, 0};
+            rc = postprocess(n, &Ak, dk, min_pts[p],
+                             labels + ((size_t)p * (size_t)n_eps + (size_t)k) * (size_t)n, local);
+            if (rc == 0 && stats)
+                memcpy(stats + ((size_t)p * (size_t)n_eps + (size_t)k) * 8, local, sizeof(local));
+        }
+    }
+    free(A.v);
+    free(Ak.v);
+    free(dg);
+    free(dk);
+    return rc;
+}
+
 int sng_oracle_graph(int64_t n, const int64_t *edges, int64_t n_edges, int32_t min_pts,
                      int32_t *labels, uint32_t *deg, uint64_t *stats)
 {

@@ -98,6 +98,16 @@ int sng_oracle_dbscan_similarity(const float *X, int64_t n, int32_t d, int64_t l
                                  int32_t kind, double tau, int32_t min_pts, uint64_t seed,
                                  int32_t mode, int32_t *labels, uint32_t *deg, uint64_t *stats);
 
+/* Every (eps[k], min_pts[p]) pair of a grid (Section 5 tunes eps over a
+ * grid): labels[(p*n_eps + k)*n + i] and deg[k*n + i] (deg may be NULL) equal
+ * those of sng_oracle_dbscan(eps[k], min_pts[p]) in `mode` (0 or 2); stats,
+ * if not NULL, holds 8 values per (p, k) in the same order. eps in any
+ * order, each finite and >= 0. */
+int sng_oracle_sweep(const float *X, int64_t n, int32_t d, int64_t ld, int64_t m,
+                     const double *eps, int32_t n_eps, const int32_t *min_pts, int32_t n_minpts,
+                     uint64_t seed, int32_t mode, int32_t *labels, uint32_t *deg,
+                     uint64_t *stats);
+
 /* Post-processing only, on an explicit accepted-pair list edges[2*k],
  * edges[2*k+1] (each pair counted once per occurrence, self-pairs rejected
  * with -1). */
