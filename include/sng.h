@@ -70,7 +70,8 @@ extern "C" {
 typedef enum {
     SNG_OK = 0,
     SNG_EINVAL = -1,     /* invalid argument (null pointer, d < 1, ld < d, eps < 0, ...) */
-    SNG_ERANGE = -2,     /* a size beyond what the kernels index (n > 2^31-1, m > 2^31, ...) */
+    SNG_ERANGE = -2,     /* a size beyond what the kernels index (n > 2^31-1, m > 2^31, sweep
+                            grids beyond 64 eps or 16 MinPts values, ...) */
     SNG_EWORKSPACE = -3, /* workspace missing or smaller than required */
     SNG_EHIP = -4,       /* a HIP runtime call or kernel launch failed */
     SNG_EOVERFLOW = -5,  /* reported by sng_stats_read: a device queue overflowed */
@@ -296,10 +297,13 @@ int sng_graph_labels(int64_t n, const int32_t *edges, int64_t n_edges, int32_t m
                      void *stream);
 
 /* Hyperparameter sweep: every (eps[k], min_pts[p]) pair of a grid from one
- * sampled-distance pass (same sampler for all pairs). eps: host, n_eps values,
- * strictly increasing, n_eps <= 255. min_pts: host, n_minpts values.
- * labels: device i32 [n_minpts][n_eps][n]; degrees: device u32 [n_eps][n] or
- * NULL. Each labels[p][k] equals sng_dbscan(..., eps[k], min_pts[p], ...). */
+ * sampled-distance pass (same sampler for all pairs; Section 5 tunes eps over
+ * a grid). eps: host, n_eps values, finite, >= 0 and strictly increasing,
+ * 1 <= n_eps <= 64. min_pts: host, 1 <= n_minpts <= 16 values, any int32.
+ * More values than these limits: SNG_ERANGE, as when n * n_eps * n_minpts
+ * exceeds 2^40. labels: device i32 [n_minpts][n_eps][n]; degrees: device
+ * u32 [n_eps][n] or NULL. Each labels[p][k] equals sng_dbscan(..., eps[k],
+ * min_pts[p], ...), and degrees[k] its degrees. */
 int sng_sweep_workspace_size(int64_t n, int32_t d, int64_t m, int32_t n_eps, int32_t n_minpts,
                              size_t *bytes);
 int sng_dbscan_sweep(const float *X, int64_t n, int32_t d, int64_t ld, double s,
@@ -310,7 +314,13 @@ int sng_dbscan_sweep(const float *X, int64_t n, int32_t d, int64_t ld, double s,
 /* Batch of independent instances solved together (each equal to its own
  * sng_dbscan call). Arrays of length `count` are host arrays; X[k],
  * labels[k], degrees[k] are device pointers (degrees may be NULL or hold
- * NULL entries). All instances share d. */
+ * NULL entries). All instances share d; count <= 2^20.
+ * Unlike the other calls, sng_dbscan_batch and sng_batch_plan_create copy
+ * the batch's instance tables from host memory into the workspace and wait
+ * for `stream` to finish that copy (work enqueued on it before the call
+ * included) before returning, so neither may be called while `stream` is
+ * being captured into a HIP graph; the plan is the captured form. The
+ * kernels are enqueued without waiting. */
 int sng_batch_workspace_size(int32_t count, const int64_t *n, int32_t d, const double *s,
                              size_t *bytes);
 int sng_dbscan_batch(int32_t count, const float *const *X, const int64_t *n, int32_t d,
@@ -321,7 +331,8 @@ int sng_dbscan_batch(int32_t count, const float *const *X, const int64_t *n, int
 
 /* Captured form of sng_dbscan_batch: the plan records every pass of the
  * batch into one HIP graph once; each launch replays it on `stream` with the
- * same buffers (their contents may change between launches). */
+ * same buffers (their contents may change between launches) and returns
+ * without waiting. */
 typedef struct sng_batch_plan sng_batch_plan;
 int sng_batch_plan_create(int32_t count, const float *const *X, const int64_t *n, int32_t d,
                           const int64_t *ld, const double *s, const double *eps,

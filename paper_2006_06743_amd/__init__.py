@@ -138,7 +138,7 @@ def sample(n: int, d: int, m: int, seed: int, ws: torch.Tensor):
 
 def _config_of(c) -> Config:
     return Config(c.lanes_per_pair, c.chunks_per_wave, c.stage_lds, c.prefetch, c.schedule,
-                  c.reuse_sample, c.out_degree)
+                  c.reuse_sample, c.out_degree, c.simple_graph)
 
 
 def autotune(X: torch.Tensor, m: int, eps: float, seed: int, trials: int = 2,

@@ -213,3 +213,40 @@ def test_simple_graph_config_and_workspace(lib):
     assert lib.sng_workspace_size(1000, 3, 50, 0x100, ctypes.byref(c)) == 0
     assert lib.sng_dbscan(fake, 1000, 3, 3, 0.05, 1.0, 3, 1, lab, None, ws, c.value,
                           ctypes.byref(simple), None) == -3
+
+
+def test_sweep_limits_as_documented(lib):
+    """sng.h: 1 <= n_eps <= 64 finite, >= 0, strictly increasing eps;
+    1 <= n_minpts <= 16; beyond the limits SNG_ERANGE, before any launch."""
+    fake = ctypes.c_void_p(0x1000)
+    ws = ctypes.c_void_p(0x2000)
+    lab = ctypes.c_void_p(0x3000)
+    b = ctypes.c_size_t()
+
+    def sweep(eps, mps, wsb=0):
+        e = (ctypes.c_double * max(1, len(eps)))(*eps)
+        p = (ctypes.c_int32 * max(1, len(mps)))(*mps)
+        return lib.sng_dbscan_sweep(fake, 10, 2, 2, 0.5, e, len(eps), p, len(mps), 1, lab, None,
+                                    ws, wsb, None, None)
+
+    grid = [0.1 * (k + 1) for k in range(64)]
+    assert sweep(grid, [2] * 16) == -3            # limits met: only the workspace is short
+    assert sweep(grid + [7.0], [2]) == -2         # 65 eps values
+    assert sweep([0.1], [2] * 17) == -2           # 17 MinPts values
+    assert sweep([], [2]) == -1 and sweep([0.1], []) == -1
+    assert sweep([0.2, 0.1], [2]) == -1           # not increasing
+    assert sweep([0.1, 0.1], [2]) == -1           # not strictly increasing
+    assert sweep([-0.1, 0.1], [2]) == -1
+    assert sweep([0.1, float("inf")], [2]) == -1
+    assert sweep([0.0, 0.1], [-5, 2**31 - 1]) == -3
+    assert lib.sng_sweep_workspace_size(10, 2, 5, 64, 16, ctypes.byref(b)) == 0
+    assert lib.sng_sweep_workspace_size(10, 2, 5, 65, 16, ctypes.byref(b)) == -2
+    assert lib.sng_sweep_workspace_size(10, 2, 5, 64, 17, ctypes.byref(b)) == -2
+
+
+def test_config_round_trip_keeps_every_field():
+    import paper_2006_06743_amd as sng
+    from paper_2006_06743_amd._lib import sng_config
+    c = sng_config(4, 8, 1, 16, 2, 1, 1, 1)
+    back = sng._config_of(c)
+    assert back == sng.Config(4, 8, 1, 16, 2, 1, 1, 1)
