@@ -344,6 +344,27 @@ int sng_batch_plan_launch(sng_batch_plan *plan, void *stream);
  * one of its HIP graph or stream handles failed. */
 int sng_batch_plan_destroy(sng_batch_plan *plan);
 
+/* Allocation-free form of sng_dbscan, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc). Arguments, results and errors are those
+ * of sng_dbscan, without workspace: the call uses a static device array of
+ * SNG_NOALLOC_SCRATCH_BYTES (32 MiB) that every GPU the library runs on
+ * holds until the process ends, and calls no allocating routine. Inputs and
+ * outputs are still the caller's. SNG_ERANGE when the workspace sng_dbscan
+ * would need (sng_workspace_size with SNG_WS_DIRECT, plus
+ * SNG_WS_SIMPLE_GRAPH for the simple-graph mode) exceeds the array, e.g.
+ * n = 1e6 points with more than about 200 samples each; SNG_EINVAL with
+ * reuse_sample; SNG_EHIP if the array's device address cannot be obtained.
+ * All calls on one GPU share its array, which keeps the last call's
+ * contents (each call clears what it uses): calls that overlap on one GPU,
+ * on any streams or host threads, race and give undefined results, so the
+ * caller must order them (e.g. one stream). sng_stats_read cannot reach the
+ * array; use sng_dbscan for counters. */
+#define SNG_NOALLOC_SCRATCH_BYTES ((size_t)32 << 20)
+int sng_dbscan_noalloc(const float *X, int64_t n, int32_t d, int64_t ld, double s, double eps,
+                       int32_t min_pts, uint64_t seed, int32_t *labels, uint32_t *degrees,
+                       const sng_config *cfg, void *stream);
+
 /* Copies the counters of the last call that used `workspace` (waits for
  * `stream`). Returns SNG_EOVERFLOW if that call's queue overflowed. For a
  * batch workspace, `index` selects the instance; otherwise pass 0. */

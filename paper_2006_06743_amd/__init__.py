@@ -18,7 +18,7 @@ from . import _lib
 from ._lib import (SNG_BF16, SNG_FP16, SNG_FP32, SNG_SIM_COSINE, SNG_SIM_DOT, SNGError, check,
                    sng_config, sng_stats)
 
-__all__ = ["dbscan", "dbscan_lowp", "dbscan_similarity", "degrees", "sample", "cluster",
+__all__ = ["dbscan", "dbscan_noalloc", "dbscan_lowp", "dbscan_similarity", "degrees", "sample", "cluster",
            "compact_labels", "similarity_workspace_size", "SNG_SIM_DOT", "SNG_SIM_COSINE",
            "autotune", "autotune_lookup", "autotune_clear",
            "graph_labels", "sweep", "batch", "BatchPlan",
@@ -206,6 +206,23 @@ def dbscan(X: torch.Tensor, s: float, eps: float, min_pts: int, seed: int,
                                  ws.data_ptr(), ws.numel(), _cfg(cfg), _stream(X)),
           "sng_dbscan")
     return labels, degrees_out, ws
+
+
+def dbscan_noalloc(X: torch.Tensor, s: float, eps: float, min_pts: int, seed: int,
+                   cfg: Optional[Config] = None, labels: Optional[torch.Tensor] = None,
+                   degrees_out: Optional[torch.Tensor] = None):
+    """sng_dbscan_noalloc: SNG-DBSCAN with the library's static device
+    scratch array as workspace (the C call allocates nothing; outputs are
+    allocated here when not given). Returns (labels, degrees or None)."""
+    n, d, ld = _rows(X)
+    if labels is None:
+        labels = torch.empty(n, dtype=torch.int32, device=X.device)
+    check(_lib.load().sng_dbscan_noalloc(X.data_ptr(), n, d, ld, float(s), float(eps),
+                                         int(min_pts), int(seed), labels.data_ptr(),
+                                         degrees_out.data_ptr() if degrees_out is not None
+                                         else None, _cfg(cfg), _stream(X)),
+          "sng_dbscan_noalloc")
+    return labels, degrees_out
 
 
 def similarity_workspace_size(n: int, d: int, m: int, kind: int, flags: int = 0) -> int:

@@ -26,7 +26,7 @@ EXPORTS = [
     "sng_sweep_workspace_size", "sng_dbscan_sweep", "sng_batch_workspace_size",
     "sng_dbscan_batch", "sng_batch_plan_create", "sng_batch_plan_launch",
     "sng_batch_plan_destroy", "sng_stats_read",
-    "sng_similarity_workspace_size", "sng_dbscan_similarity",
+    "sng_similarity_workspace_size", "sng_dbscan_similarity", "sng_dbscan_noalloc",
 ]
 
 
@@ -74,6 +74,8 @@ def load() -> ctypes.CDLL:
         "sng_cluster": ([P, i64, i32, i64, i64, dbl, u64, i32, P, P, P, sz, P], ctypes.c_int),
         "sng_dbscan": ([P, i64, i32, i64, dbl, dbl, i32, u64, P, P, P, sz, cfgp, P],
                        ctypes.c_int),
+        "sng_dbscan_noalloc": ([P, i64, i32, i64, dbl, dbl, i32, u64, P, P, cfgp, P],
+                               ctypes.c_int),
         "sng_dbscan_lowp": ([P, i64, i32, i64, P, i64, f32, i32, dbl, dbl, i32, u64, P, P, P,
                              sz, cfgp, P], ctypes.c_int),
         "sng_similarity_workspace_size": ([i64, i32, i64, i32, i32, ctypes.POINTER(sz)],

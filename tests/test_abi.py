@@ -250,3 +250,21 @@ def test_config_round_trip_keeps_every_field():
     c = sng_config(4, 8, 1, 16, 2, 1, 1, 1)
     back = sng._config_of(c)
     assert back == sng.Config(4, 8, 1, 16, 2, 1, 1, 1)
+
+
+def test_noalloc_limits_before_any_device_work(lib):
+    """sng_dbscan_noalloc refuses, before touching the device, a call whose
+    workspace exceeds SNG_NOALLOC_SCRATCH_BYTES (32 MiB) and reuse_sample."""
+    from paper_2006_06743_amd._lib import sng_config
+    fake = ctypes.c_void_p(0x1000)
+    lab = ctypes.c_void_p(0x3000)
+    b = ctypes.c_size_t()
+    assert lib.sng_workspace_size(10**6, 16, 1000, 0x100, ctypes.byref(b)) == 0
+    assert b.value > 32 << 20
+    assert lib.sng_dbscan_noalloc(fake, 10**6, 16, 16, 0.001, 2.0, 5, 2, lab, None, None,
+                                  None) == -2
+    assert lib.sng_dbscan_noalloc(fake, 10, 2, 2, -0.5, 1.0, 3, 1, lab, None, None, None) == -1
+    assert lib.sng_dbscan_noalloc(fake, 10, 0, 2, 0.5, 1.0, 3, 1, lab, None, None, None) == -1
+    reuse = sng_config(0, 0, 0, 0, 0, 1, 0, 0)
+    assert lib.sng_dbscan_noalloc(fake, 10, 2, 2, 0.5, 1.0, 3, 1, lab, None,
+                                  ctypes.byref(reuse), None) == -1
