@@ -181,14 +181,27 @@ bool bucket_geometry(int64_t n, int d, int64_t m, bool force, BucketGeom *g)
     // when X does not fit one XCD's L2
     if (!force && (d * 4 >= 128 || (uint64_t)n * (uint64_t)d * 4 <= ((uint64_t)8 << 20)))
         return false;
-    // partner block: at most 2^16 rows and about half a MB of rows
+    // partner block: rows of at most kLdsMaxD floats take the largest power
+    // of two of rows that fits kLdsBlockBytes (the evaluate kernel then holds
+    // a whole block in LDS), unless that makes more than kMaxPartnerBlocks
+    // blocks; otherwise at most 2^16 rows and about half a MB of rows, which
+    // stay in one XCD's L2
+    auto blocks_of = [&](int bs) { return (uint64_t)((n + ((int64_t)1 << bs) - 1) >> bs); };
     int bs = 16;
-    while (bs > 6 && ((uint64_t)1 << bs) * (uint64_t)d * 4 > (512u << 10))
-        --bs;
+    if (d <= kLdsMaxD) {
+        while (bs > 6 && ((uint64_t)1 << bs) * (uint64_t)d * 4 > kLdsBlockBytes)
+            --bs;
+        b.lds = blocks_of(bs) <= kMaxPartnerBlocks ? 1u : 0u;
+    }
+    if (!b.lds) {
+        bs = 16;
+        while (bs > 6 && ((uint64_t)1 << bs) * (uint64_t)d * 4 > (512u << 10))
+            --bs;
+    }
     b.bshift = (uint32_t)bs;
-    b.NJ = (uint32_t)((n + ((int64_t)1 << bs) - 1) >> bs);
-    if (b.NJ > kMaxPartnerBlocks)
+    if (blocks_of(bs) > kMaxPartnerBlocks)
         return false;
+    b.NJ = (uint32_t)blocks_of(bs);
     const uint64_t C = (uint64_t)((m + 3) / 4);
     const uint64_t calls = (uint64_t)n * C;
     b.ranges = (calls + kRangeCalls - 1) / kRangeCalls;
@@ -201,6 +214,23 @@ bool bucket_geometry(int64_t n, int d, int64_t m, bool force, BucketGeom *g)
     if (g)
         *g = b;
     return true;
+}
+
+unsigned lds_eval_blocks()
+{
+    // one workgroup per compute unit of the current device (256 on MI355X)
+    static int cus[64];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64)
+        return 256;
+    if (cus[dev] <= 0) {
+        int c = 0;
+        if (hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            c <= 0)
+            c = 256;
+        cus[dev] = c;
+    }
+    return (unsigned)cus[dev];
 }
 
 size_t bucket_bytes(const BucketGeom &g)

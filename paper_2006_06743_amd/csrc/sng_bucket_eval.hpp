@@ -147,9 +147,13 @@ __device__ __forceinline__ bool sample_ok(const Inst &I, const BucketGeom &B)
 constexpr uint32_t kTicketRanges = 16;
 static_assert(kTicketRanges <= kWave, "one lane per segment of a ticket");
 
-template <class Row, int OB, bool kBuf, class Pol>
+//
+// kLds: the partner rows come from `blk`, the whole partner block J staged in
+// LDS (Row::kD floats per row, packed), instead of global memory.
+template <class Row, int OB, bool kBuf, bool kLds, class Pol>
 __device__ __forceinline__ void eval_ticket(const Inst &I, const BucketGeom &B, Pol &pol,
-                                            uint64_t r0, uint32_t T, uint32_t J, Tally &tally)
+                                            uint64_t r0, uint32_t T, uint32_t J, Tally &tally,
+                                            const float *blk)
 {
     constexpr int G = Row::kG;
     constexpr int P = 4 * OB;  // records in flight per group
@@ -252,13 +256,18 @@ __device__ __forceinline__ void eval_ticket(const Inst &I, const BucketGeom &B, 
             }
             const uint32_t sj = live[k] ? cj[k] : 0u;  // row 0 always exists
             const uint32_t si = live[k] ? ii[k] : 0u;
-            if constexpr (kBuf) {
+            if constexpr (kLds) {
+                // row 0 of the block is staged whenever the block exists
+                bj[k] = Row::fetch_lds(blk + (live[k] ? (v[k] & 0xFFFFu) : 0u) * Row::kD);
+            } else if constexpr (kBuf) {
                 bj[k] = Row::fetchb(rs, __umul24(sj, ld4), q, d);
-                bi[k] = Row::fetchb(rs, __umul24(si, ld4), q, d);
             } else {
                 bj[k] = Row::fetch(X + (int64_t)sj * ld, q, d);
-                bi[k] = Row::fetch(X + (int64_t)si * ld, q, d);
             }
+            if constexpr (kBuf)
+                bi[k] = Row::fetchb(rs, __umul24(si, ld4), q, d);
+            else
+                bi[k] = Row::fetch(X + (int64_t)si * ld, q, d);
         }
 #pragma unroll
         for (int k = 0; k < P; ++k) {
@@ -319,7 +328,8 @@ __device__ __forceinline__ void eval_all(const Inst &I, const BucketGeom &B, Pol
             const uint64_t r0 = (e - jl * tpj) * kTicketRanges;
             const uint64_t left = B.ranges - r0;
             const uint32_t T = (uint32_t)(left < kTicketRanges ? left : kTicketRanges);
-            eval_ticket<Row, OB, kBuf>(I, B, pol, r0, T, (uint32_t)(x + jl * kXcds), tally);
+            eval_ticket<Row, OB, kBuf, false>(I, B, pol, r0, T, (uint32_t)(x + jl * kXcds), tally,
+                                              nullptr);
         }
     }
 }
@@ -376,6 +386,140 @@ __global__ __launch_bounds__(256) void k_bkt_eval_sweep(Inst I, BucketGeom B, Sw
 }
 
 // ---------------------------------------------------------------------------
+// LDS form, for rows of at most kLdsMaxD floats (blocks of at most
+// kLdsBlockBytes). One workgroup per compute unit takes work items (chunk of
+// kLdsChunkRanges generator ranges, partner block J) from a global counter in
+// chunk-major order, stages block J whole in LDS with coalesced loads, and
+// its wavefronts decide every record of the item's ranges for that block:
+// wavefront w takes tickets of kLdsTicketRanges ranges w, w + waves, ... .
+// Partner rows are then LDS reads instead of divergent global gathers; the
+// source rows of a ticket are few and consecutive (a range covers
+// kRangeCalls / ceil(m/4) points), so their global loads stay coalesced, and
+// the chunk-major order keeps a chunk's source rows in L2 while its blocks
+// are visited.
+// ---------------------------------------------------------------------------
+constexpr uint32_t kLdsThreads = 1024;
+constexpr uint32_t kLdsWaves = kLdsThreads / kWave;
+constexpr uint32_t kLdsTicketRanges = 64;
+constexpr uint64_t kLdsChunkRanges = 16384;
+static_assert(kLdsTicketRanges <= kWave, "one lane per segment of a ticket");
+
+template <int D, int OB, bool kBuf, class Pol>
+__device__ __forceinline__ void eval_all_lds(const Inst &I, const BucketGeom &B, Pol &pol,
+                                             Tally &tally, float *blk,
+                                             unsigned long long *s_item)
+{
+    using Row = SmallRow<D>;
+    const uint32_t rows = 1u << B.bshift;
+    const uint64_t chunks = (B.ranges + kLdsChunkRanges - 1) / kLdsChunkRanges;
+    const uint64_t items = chunks * B.NJ;
+    const uint32_t wave = threadIdx.x / kWave;
+    for (;;) {
+        __syncthreads();  // the last item's LDS reads are done, s_item is free
+        if (threadIdx.x == 0)
+            *s_item = atomicAdd(B.queue, 1ull);
+        __syncthreads();
+        const uint64_t it = *s_item;
+        if (it >= items)
+            break;  // uniform over the workgroup
+        const uint64_t c = it / B.NJ;
+        const uint32_t J = (uint32_t)(it - c * B.NJ);
+        const uint32_t j0 = J << B.bshift;
+        const uint32_t nr = min(rows, I.n - j0);
+        for (uint32_t e = threadIdx.x; e < nr * (uint32_t)D; e += kLdsThreads) {
+            const uint32_t r = e / (uint32_t)D;
+            blk[e] = I.X[(int64_t)(j0 + r) * I.ld + (e - r * (uint32_t)D)];
+        }
+        __syncthreads();
+        const uint64_t rlo = c * kLdsChunkRanges;
+        const uint64_t rhi = min(B.ranges, rlo + kLdsChunkRanges);
+        for (uint64_t r0 = rlo + (uint64_t)wave * kLdsTicketRanges; r0 < rhi;
+             r0 += (uint64_t)kLdsWaves * kLdsTicketRanges) {
+            const uint64_t left = rhi - r0;
+            const uint32_t T = (uint32_t)(left < kLdsTicketRanges ? left : kLdsTicketRanges);
+            eval_ticket<Row, OB, kBuf, true>(I, B, pol, r0, T, J, tally, blk);
+        }
+    }
+}
+
+template <int D, bool kBuf, int kQ>
+__global__ __launch_bounds__(kLdsThreads) void k_bkt_eval_lds(Inst I, BucketGeom B)
+{
+    extern __shared__ float lds_blk[];
+    __shared__ unsigned long long s_item;
+    if (!sample_ok(I, B))
+        return;
+    BucketPlainPolicy<kQ> pol;
+    pol.out_deg = I.out_deg;
+    pol.X = I.X;
+    pol.ld = I.ld;
+    pol.d = I.d;
+    pol.deg = I.deg;
+    pol.mask = I.mask;
+    pol.lo = I.lo;
+    pol.hi = I.hi;
+    pol.eps2 = I.eps2;
+    pol.sim = I.sim;
+    Tally t;
+    eval_all_lds<D, 1, kBuf>(I, B, pol, t, lds_blk, &s_item);
+    commit_tally(t, I.cnt);
+}
+
+template <int D, bool kBuf>
+__global__ __launch_bounds__(kLdsThreads) void k_bkt_eval_lds_sweep(Inst I, BucketGeom B,
+                                                                    SweepArgs S)
+{
+    extern __shared__ float lds_blk[];
+    __shared__ unsigned long long s_item;
+    __shared__ float s_lo[kSweepMaxK], s_hi[kSweepMaxK];
+    __shared__ double s_e2[kSweepMaxK];
+    if (!sample_ok(I, B))
+        return;
+    for (int k = threadIdx.x; k < S.K; k += blockDim.x) {
+        s_lo[k] = S.c.lo[k];
+        s_hi[k] = S.c.hi[k];
+        s_e2[k] = S.c.e2[k];
+    }
+    BucketSweepPolicy pol;
+    pol.out_deg = I.out_deg;
+    pol.X = I.X;
+    pol.ld = I.ld;
+    pol.d = I.d;
+    pol.hist = S.hist;
+    pol.codes = reinterpret_cast<uint8_t *>(S.codes);
+    pol.lo = s_lo;
+    pol.hi = s_hi;
+    pol.e2 = s_e2;
+    pol.K = S.K;
+    pol.hi_max = S.c.hi[S.K - 1];
+    Tally t;
+    eval_all_lds<D, 1, kBuf>(I, B, pol, t, lds_blk, &s_item);  // its first barrier orders s_*
+    commit_tally(t, I.cnt);
+}
+
+// Workgroups of the LDS form: one per compute unit (a block of up to
+// kLdsBlockBytes leaves room for one workgroup per CU).
+unsigned lds_eval_blocks();
+
+// Calls fn.template operator()<D>() for the compile-time row length D = d
+// (1 <= d <= kLdsMaxD).
+template <class Fn>
+hipError_t dispatch_small_d(int d, Fn &&fn)
+{
+    switch (d) {
+    case 1: return fn.template operator()<1>();
+    case 2: return fn.template operator()<2>();
+    case 3: return fn.template operator()<3>();
+    case 4: return fn.template operator()<4>();
+    case 5: return fn.template operator()<5>();
+    case 6: return fn.template operator()<6>();
+    case 7: return fn.template operator()<7>();
+    case 8: return fn.template operator()<8>();
+    default: return hipErrorInvalidValue;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Host side of the evaluate launches.
 // ---------------------------------------------------------------------------
 // Rows are read through a buffer descriptor with 32-bit byte offsets formed
@@ -410,6 +554,19 @@ template <int kQ>
 hipError_t launch_bucket_eval(const Inst &I, const BucketGeom &B, const PassAShape &sh,
                               hipStream_t st)
 {
+    if (B.lds) {
+        const size_t lds = ((size_t)1 << B.bshift) * (size_t)I.d * sizeof(float);
+        const bool buf = use_buffer(I);
+        return dispatch_small_d(I.d, [&]<int D>() -> hipError_t {
+            if (buf)
+                hipLaunchKernelGGL((k_bkt_eval_lds<D, true, kQ>), dim3(lds_eval_blocks()),
+                                   dim3(kLdsThreads), lds, st, I, B);
+            else
+                hipLaunchKernelGGL((k_bkt_eval_lds<D, false, kQ>), dim3(lds_eval_blocks()),
+                                   dim3(kLdsThreads), lds, st, I, B);
+            return hipGetLastError();
+        });
+    }
     const bool vec_ok = ((uintptr_t)I.X % 16 == 0) && (I.ld % 4 == 0);
     return dispatch(I.d, vec_ok, sh, [&]<class Row, int OB>(uint32_t) -> hipError_t {
         if constexpr (Row::kPrefetch) {

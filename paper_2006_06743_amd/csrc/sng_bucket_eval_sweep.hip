@@ -6,6 +6,19 @@ namespace sng {
 hipError_t launch_bucket_eval_sweep(const Inst &I, const SweepArgs &S, const BucketGeom &B,
                                     const PassAShape &sh, hipStream_t st)
 {
+    if (B.lds) {
+        const size_t lds = ((size_t)1 << B.bshift) * (size_t)I.d * sizeof(float);
+        const bool buf = use_buffer(I);
+        return dispatch_small_d(I.d, [&]<int D>() -> hipError_t {
+            if (buf)
+                hipLaunchKernelGGL((k_bkt_eval_lds_sweep<D, true>), dim3(lds_eval_blocks()),
+                                   dim3(kLdsThreads), lds, st, I, B, S);
+            else
+                hipLaunchKernelGGL((k_bkt_eval_lds_sweep<D, false>), dim3(lds_eval_blocks()),
+                                   dim3(kLdsThreads), lds, st, I, B, S);
+            return hipGetLastError();
+        });
+    }
     const bool vec_ok = ((uintptr_t)I.X % 16 == 0) && (I.ld % 4 == 0);
     return dispatch(I.d, vec_ok, sh, [&]<class Row, int OB>(uint32_t) -> hipError_t {
         if constexpr (Row::kPrefetch) {

@@ -79,9 +79,14 @@ hipError_t launch_batch(const Inst *T, const BatchGeom &G, int d, bool vec_ok,
 constexpr int kXcds = 8;                    // workgroup b runs on XCD b mod 8
 constexpr uint64_t kRangeCalls = 8192;      // Philox calls per generator range (one workgroup)
 constexpr uint32_t kMaxPartnerBlocks = 1024;
+// Rows of at most kLdsMaxD floats get partner blocks of at most
+// kLdsBlockBytes, which the evaluate kernel stages in LDS whole.
+constexpr int kLdsMaxD = 8;
+constexpr uint32_t kLdsBlockBytes = 128u << 10;
 struct BucketGeom {
     uint32_t bshift;     // partner block = 2^bshift rows
     uint32_t NJ;         // partner blocks
+    uint32_t lds;        // 1: blocks sized for LDS (rows of at most kLdsMaxD floats)
     uint64_t ranges;     // generator ranges
     uint64_t region;     // records per generator range (capacity)
     uint32_t *rec;       // [ranges][region] 4-byte slot records

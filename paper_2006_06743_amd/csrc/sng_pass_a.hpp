@@ -25,11 +25,21 @@ __device__ __forceinline__ void dot_step(float2 &acc, float a, float b)
 template <int D>
 struct SmallRow {
     static constexpr int kG = 1;
+    static constexpr int kD = D;
     static constexpr bool kPrefetch = true;
     struct Buf {
         float v[D];
     };
     Buf r;
+    // A row staged in LDS as D packed floats.
+    __device__ __forceinline__ static Buf fetch_lds(const float *row)
+    {
+        Buf b;
+#pragma unroll
+        for (int k = 0; k < D; ++k)
+            b.v[k] = row[k];
+        return b;
+    }
     __device__ __forceinline__ static Buf fetch(const float *__restrict__ row, int, int)
     {
         Buf b;
