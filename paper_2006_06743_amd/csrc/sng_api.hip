@@ -325,7 +325,9 @@ int pick_bucket(const Inst &I, const sng_config *cfg, void *workspace, size_t ws
     B->start = cv.take<uint32_t>(B->ranges * 2);
     B->queue = cv.take<unsigned long long>(kXcds);
     B->hdr = I.cnt + kSampleHdr;
-    B->tag = sample_tag(I.n, I.m, (uint64_t)I.key0 | ((uint64_t)I.key1 << 32), B->bshift, layout);
+    // the block size and the record format (LDS or not) both fix the records
+    B->tag = sample_tag(I.n, I.m, (uint64_t)I.key0 | ((uint64_t)I.key1 << 32),
+                        B->bshift | (B->lds << 8), layout);
     *use = true;
     return SNG_OK;
 }

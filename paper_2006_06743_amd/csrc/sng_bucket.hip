@@ -113,8 +113,10 @@ __global__ __launch_bounds__(kGenThreads) void k_bkt_generate(Inst I, BucketGeom
                 } else {
                     const uint32_t J = j >> B.bshift;
                     kk = (J << 16) | atomicAdd(cnt + J, 1u);
-                    rr = (off << kRecOffShift) | ((uint32_t)w << 16) |
-                         (j & ((1u << B.bshift) - 1u));
+                    const uint32_t pj = j & ((1u << B.bshift) - 1u);
+                    rr = B.lds ? ((((ii - i0) << B.tc_bits) | cc) << (B.bshift + 2)) |
+                                     ((uint32_t)w << B.bshift) | pj
+                               : (off << kRecOffShift) | ((uint32_t)w << 16) | pj;
                 }
             }
             key[4 * c + w] = kk;
@@ -187,11 +189,21 @@ bool bucket_geometry(int64_t n, int d, int64_t m, bool force, BucketGeom *g)
     // blocks; otherwise at most 2^16 rows and about half a MB of rows, which
     // stay in one XCD's L2
     auto blocks_of = [&](int bs) { return (uint64_t)((n + ((int64_t)1 << bs) - 1) >> bs); };
+    const uint64_t C = (uint64_t)((m + 3) / 4);
     int bs = 16;
     if (d <= kLdsMaxD) {
         while (bs > 6 && ((uint64_t)1 << bs) * (uint64_t)d * 4 > kLdsBlockBytes)
             --bs;
-        b.lds = blocks_of(bs) <= kMaxPartnerBlocks ? 1u : 0u;
+        // the LDS record fields: the call within the point (< C) and the
+        // source's offset within its range (at most (C - 1 + kRangeCalls - 1) / C)
+        uint32_t tc = 0, so = 0;
+        while (((uint64_t)1 << tc) < C)
+            ++tc;
+        const uint64_t max_off = (C - 1 + kRangeCalls - 1) / C;
+        while (((uint64_t)1 << so) <= max_off)
+            ++so;
+        b.tc_bits = tc;
+        b.lds = (blocks_of(bs) <= kMaxPartnerBlocks && (uint32_t)bs + 2 + tc + so <= 32) ? 1u : 0u;
     }
     if (!b.lds) {
         bs = 16;
@@ -202,7 +214,6 @@ bool bucket_geometry(int64_t n, int d, int64_t m, bool force, BucketGeom *g)
     if (blocks_of(bs) > kMaxPartnerBlocks)
         return false;
     b.NJ = (uint32_t)blocks_of(bs);
-    const uint64_t C = (uint64_t)((m + 3) / 4);
     const uint64_t calls = (uint64_t)n * C;
     b.ranges = (calls + kRangeCalls - 1) / kRangeCalls;
     b.region = kRangeSlots;

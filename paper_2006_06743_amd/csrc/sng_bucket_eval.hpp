@@ -45,6 +45,12 @@ struct BucketPlainPolicy {
             return 0;
         return recheck(i, j, t, q);
     }
+    // false only where decide() surely rejects (so record() does nothing)
+    __device__ __forceinline__ bool may_act(float F) const { return !(F > hi); }
+    __device__ __forceinline__ bool may_act_dot(float P, float Q) const
+    {
+        return sim.band_dot(P, Q) != 0;
+    }
     __device__ __forceinline__ int decide_dot(float P, float Q, uint32_t i, uint32_t j, Tally &t,
                                               int q)
     {
@@ -79,6 +85,10 @@ struct BucketSweepPolicy {
     int K;
     float hi_max;
     static constexpr bool kDot = false;
+
+    // false only where decide() surely returns K (so record() does nothing)
+    __device__ __forceinline__ bool may_act(float F) const { return F <= hi_max; }
+    __device__ __forceinline__ bool may_act_dot(float, float) const { return true; }
 
     __device__ __forceinline__ int decide(float F, uint32_t i, uint32_t j, Tally &t, int q)
     {
@@ -147,13 +157,9 @@ __device__ __forceinline__ bool sample_ok(const Inst &I, const BucketGeom &B)
 constexpr uint32_t kTicketRanges = 16;
 static_assert(kTicketRanges <= kWave, "one lane per segment of a ticket");
 
-//
-// kLds: the partner rows come from `blk`, the whole partner block J staged in
-// LDS (Row::kD floats per row, packed), instead of global memory.
-template <class Row, int OB, bool kBuf, bool kLds, class Pol>
+template <class Row, int OB, bool kBuf, class Pol>
 __device__ __forceinline__ void eval_ticket(const Inst &I, const BucketGeom &B, Pol &pol,
-                                            uint64_t r0, uint32_t T, uint32_t J, Tally &tally,
-                                            const float *blk)
+                                            uint64_t r0, uint32_t T, uint32_t J, Tally &tally)
 {
     constexpr int G = Row::kG;
     constexpr int P = 4 * OB;  // records in flight per group
@@ -256,18 +262,13 @@ __device__ __forceinline__ void eval_ticket(const Inst &I, const BucketGeom &B, 
             }
             const uint32_t sj = live[k] ? cj[k] : 0u;  // row 0 always exists
             const uint32_t si = live[k] ? ii[k] : 0u;
-            if constexpr (kLds) {
-                // row 0 of the block is staged whenever the block exists
-                bj[k] = Row::fetch_lds(blk + (live[k] ? (v[k] & 0xFFFFu) : 0u) * Row::kD);
-            } else if constexpr (kBuf) {
+            if constexpr (kBuf) {
                 bj[k] = Row::fetchb(rs, __umul24(sj, ld4), q, d);
+                bi[k] = Row::fetchb(rs, __umul24(si, ld4), q, d);
             } else {
                 bj[k] = Row::fetch(X + (int64_t)sj * ld, q, d);
-            }
-            if constexpr (kBuf)
-                bi[k] = Row::fetchb(rs, __umul24(si, ld4), q, d);
-            else
                 bi[k] = Row::fetch(X + (int64_t)si * ld, q, d);
+            }
         }
 #pragma unroll
         for (int k = 0; k < P; ++k) {
@@ -328,8 +329,7 @@ __device__ __forceinline__ void eval_all(const Inst &I, const BucketGeom &B, Pol
             const uint64_t r0 = (e - jl * tpj) * kTicketRanges;
             const uint64_t left = B.ranges - r0;
             const uint32_t T = (uint32_t)(left < kTicketRanges ? left : kTicketRanges);
-            eval_ticket<Row, OB, kBuf, false>(I, B, pol, r0, T, (uint32_t)(x + jl * kXcds), tally,
-                                              nullptr);
+            eval_ticket<Row, OB, kBuf>(I, B, pol, r0, T, (uint32_t)(x + jl * kXcds), tally);
         }
     }
 }
@@ -402,24 +402,206 @@ constexpr uint32_t kLdsThreads = 1024;
 constexpr uint32_t kLdsWaves = kLdsThreads / kWave;
 constexpr uint32_t kLdsTicketRanges = 64;
 constexpr uint64_t kLdsChunkRanges = 16384;
+constexpr int kLdsWindows = 4;  // windows decided per iteration of a wavefront
 static_assert(kLdsTicketRanges <= kWave, "one lane per segment of a ticket");
 
-template <int D, int OB, bool kBuf, class Pol>
+// One ticket of the LDS form: the records of partner block J from T <= 64
+// consecutive ranges (segments), one lane per pair. The wavefront walks the
+// segments in order in windows of up to 64 records of one segment (a
+// segment holds about kRangeCalls*4/NJ records, so most take one window),
+// so a window's record base and first source are scalars. It decides P
+// windows per iteration and loads the next P windows' records (and source
+// rows) before deciding the current ones, to keep loads in flight. The
+// partner row is read from `blk`, the staged block. Records carry the
+// source's offset within its range and the call within the point as bit
+// fields (BucketGeom::lds), so a source index is one add.
+// kLaneRows (every range spans at most 64 sources): lane k holds source row
+// i0 + k of a window's segment, loaded with one coalesced load, and each
+// lane takes its source row from there by a cross-lane permute; otherwise
+// each lane loads its source row. Every record is filtered in binary32
+// first, and the decision and bookkeeping run only when some lane may accept
+// or must recheck, so windows of rejections cost the filter alone.
+template <int D, int P, bool kBuf, bool kLaneRows, class Pol>
+__device__ __forceinline__ void eval_ticket_lds(const Inst &I, const BucketGeom &B, Pol &pol,
+                                                uint64_t r0, uint32_t T, uint32_t J,
+                                                Tally &tally, const float *blk)
+{
+    using Row = SmallRow<D>;
+    using Buf = typename Row::Buf;
+    const int lane = lane_id();
+    const __amdgpu_buffer_rsrc_t rrec =
+        buf_rsrc(B.rec + r0 * B.region, (uint32_t)(T * B.region * sizeof(uint32_t)));
+    uint32_t cnt_l = 0, i0_l = 0, base_l = 0;
+    if ((uint32_t)lane < T) {
+        const uint64_t r = r0 + (uint64_t)lane;
+        base_l = (uint32_t)lane * (uint32_t)B.region + B.seg[(r * B.NJ + J) * 2 + 0];
+        cnt_l = B.seg[(r * B.NJ + J) * 2 + 1];
+        i0_l = B.start[2 * r + 0];
+    }
+    uint64_t nonempty = __ballot(cnt_l > 0);  // segments not yet entered
+    if (nonempty == 0)
+        return;  // wave-uniform
+
+    const uint32_t jbase = J << B.bshift;
+    const uint32_t pmask = (1u << B.bshift) - 1u;
+    const uint32_t si_shift = B.bshift + 2 + B.tc_bits;
+    const float *__restrict__ X = I.X;
+    const int64_t ld = I.ld;
+    const uint32_t ld4 = (uint32_t)ld * 4u;
+    __amdgpu_buffer_rsrc_t rs;
+    if constexpr (kBuf)
+        rs = buf_rsrc(X, B.x_bytes);
+    auto row_at = [&](uint32_t r) -> Buf {
+        if constexpr (kBuf)
+            return Row::fetchb(rs, __umul24(r, ld4), 0, D);
+        else
+            return Row::fetch(X + (int64_t)r * ld, 0, D);
+    };
+
+    // scalar walker: the current segment (count, record base, first source)
+    // and offset o; `left` false once every window has been handed out
+    uint32_t cnt = 0, base = 0, src = 0, o = 0;
+    bool left = true;
+    auto enter = [&]() {
+        const int sg = __builtin_ctzll(nonempty);
+        nonempty &= nonempty - 1;
+        cnt = (uint32_t)__builtin_amdgcn_readlane((int)cnt_l, sg);
+        base = (uint32_t)__builtin_amdgcn_readlane((int)base_l, sg);
+        src = (uint32_t)__builtin_amdgcn_readlane((int)i0_l, sg);
+        o = 0;
+    };
+    enter();
+    // a window: its first record, source and record count (0: none)
+    uint32_t w_rec[P], w_src[P], w_n[P];
+    auto take = [&](int k) {
+        w_rec[k] = base + o;
+        w_src[k] = src;
+        w_n[k] = left ? min(cnt - o, (uint32_t)kWave) : 0u;
+        if (!left)
+            return;
+        if (o + kWave < cnt)
+            o += kWave;
+        else if (nonempty != 0)
+            enter();
+        else
+            left = false;
+    };
+    uint32_t nv[P];
+    Buf nrow[P];
+    auto issue = [&]() {  // loads of the windows in w_* (harmless ones for empty windows)
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            if constexpr (kLaneRows) {
+                const uint32_t r = w_src[k] + (uint32_t)lane;
+                nrow[k] = row_at(r < I.n ? r : I.n - 1u);
+            }
+            nv[k] = __builtin_amdgcn_raw_buffer_load_b32(rrec, (int)((w_rec[k] + lane) * 4u), 0,
+                                                        0);
+        }
+    };
+#pragma unroll
+    for (int k = 0; k < P; ++k)
+        take(k);
+    issue();
+    for (;;) {  // wave-uniform
+        uint32_t v[P], c_src[P], c_n[P];
+        Buf crow[P];
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            v[k] = nv[k];
+            crow[k] = nrow[k];
+            c_src[k] = w_src[k];
+            c_n[k] = w_n[k];
+        }
+        if (c_n[0] == 0)
+            break;  // nothing was handed out
+#pragma unroll
+        for (int k = 0; k < P; ++k)
+            take(k);
+        issue();  // the next P windows load while these are decided
+
+        uint32_t ii[P], cj[P];
+        bool live[P];
+        Buf bi[P], bj[P];
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            live[k] = (uint32_t)lane < c_n[k];
+            const uint32_t so = v[k] >> si_shift;
+            ii[k] = c_src[k] + so;
+            const uint32_t off = v[k] & pmask;
+            cj[k] = jbase + off;
+            if (live[k] && !(ii[k] < I.n && cj[k] < I.n && (!kLaneRows || so < (uint32_t)kWave))) {
+                live[k] = false;  // never for a valid sample
+                atomicAdd(I.cnt + kCntOverflow, 1ull);
+            }
+            if constexpr (kLaneRows) {
+#pragma unroll
+                for (int e = 0; e < D; ++e)
+                    bi[k].v[e] =
+                        __int_as_float(__shfl(__float_as_int(crow[k].v[e]), (int)(so & 63u)));
+            } else {
+                bi[k] = row_at(live[k] ? ii[k] : 0u);  // row 0 always exists
+            }
+            // row 0 of the block is staged whenever the block exists
+            bj[k] = Row::fetch_lds(blk + (live[k] ? off : 0u) * (uint32_t)D);
+        }
+        float F[P], Q[P];
+        bool act = false;
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            if constexpr (Pol::kDot) {
+                const float2 pq = Row::partial2_dot(bi[k], bj[k], 0, D);
+                F[k] = pq.x;
+                Q[k] = pq.y;
+                act |= live[k] && pol.may_act_dot(F[k], Q[k]);
+            } else {
+                F[k] = Row::partial2(bi[k], bj[k], 0, D);
+                Q[k] = 0.0f;
+                act |= live[k] && pol.may_act(F[k]);
+            }
+        }
+        if (__ballot(act) == 0)
+            continue;  // wave-uniform: every live slot here is surely rejected
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            if (!live[k])
+                continue;
+            int res;
+            if constexpr (Pol::kDot)
+                res = pol.decide_dot(F[k], Q[k], ii[k], cj[k], tally, 0);
+            else
+                res = pol.decide(F[k], ii[k], cj[k], tally, 0);
+            const uint32_t vk = v[k], ik = ii[k];
+            pol.record(res, ik, cj[k],
+                       [&]() {
+                           return (uint64_t)ik * I.C +
+                                  ((vk >> (B.bshift + 2)) & ((1u << B.tc_bits) - 1u));
+                       },
+                       (int)((vk >> B.bshift) & 3u), 0, tally);
+        }
+    }
+}
+
+template <int D, bool kBuf, bool kLaneRows, class Pol>
 __device__ __forceinline__ void eval_all_lds(const Inst &I, const BucketGeom &B, Pol &pol,
                                              Tally &tally, float *blk,
                                              unsigned long long *s_item)
 {
-    using Row = SmallRow<D>;
     const uint32_t rows = 1u << B.bshift;
     const uint64_t chunks = (B.ranges + kLdsChunkRanges - 1) / kLdsChunkRanges;
     const uint64_t items = chunks * B.NJ;
-    const uint32_t wave = threadIdx.x / kWave;
+    // wave index and item in scalar registers (uniform to the compiler)
+    const uint32_t wave = (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
     for (;;) {
         __syncthreads();  // the last item's LDS reads are done, s_item is free
         if (threadIdx.x == 0)
             *s_item = atomicAdd(B.queue, 1ull);
         __syncthreads();
-        const uint64_t it = *s_item;
+        const unsigned long long got = *s_item;
+        const uint64_t it =
+            ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(got >> 32))
+             << 32) |
+            (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)got);
         if (it >= items)
             break;  // uniform over the workgroup
         const uint64_t c = it / B.NJ;
@@ -437,12 +619,12 @@ __device__ __forceinline__ void eval_all_lds(const Inst &I, const BucketGeom &B,
              r0 += (uint64_t)kLdsWaves * kLdsTicketRanges) {
             const uint64_t left = rhi - r0;
             const uint32_t T = (uint32_t)(left < kLdsTicketRanges ? left : kLdsTicketRanges);
-            eval_ticket<Row, OB, kBuf, true>(I, B, pol, r0, T, J, tally, blk);
+            eval_ticket_lds<D, kLdsWindows, kBuf, kLaneRows>(I, B, pol, r0, T, J, tally, blk);
         }
     }
 }
 
-template <int D, bool kBuf, int kQ>
+template <int D, bool kBuf, bool kLaneRows, int kQ>
 __global__ __launch_bounds__(kLdsThreads) void k_bkt_eval_lds(Inst I, BucketGeom B)
 {
     extern __shared__ float lds_blk[];
@@ -461,11 +643,11 @@ __global__ __launch_bounds__(kLdsThreads) void k_bkt_eval_lds(Inst I, BucketGeom
     pol.eps2 = I.eps2;
     pol.sim = I.sim;
     Tally t;
-    eval_all_lds<D, 1, kBuf>(I, B, pol, t, lds_blk, &s_item);
+    eval_all_lds<D, kBuf, kLaneRows>(I, B, pol, t, lds_blk, &s_item);
     commit_tally(t, I.cnt);
 }
 
-template <int D, bool kBuf>
+template <int D, bool kBuf, bool kLaneRows>
 __global__ __launch_bounds__(kLdsThreads) void k_bkt_eval_lds_sweep(Inst I, BucketGeom B,
                                                                     SweepArgs S)
 {
@@ -493,8 +675,17 @@ __global__ __launch_bounds__(kLdsThreads) void k_bkt_eval_lds_sweep(Inst I, Buck
     pol.K = S.K;
     pol.hi_max = S.c.hi[S.K - 1];
     Tally t;
-    eval_all_lds<D, 1, kBuf>(I, B, pol, t, lds_blk, &s_item);  // its first barrier orders s_*
+    eval_all_lds<D, kBuf, kLaneRows>(I, B, pol, t, lds_blk, &s_item);  // its first barrier orders s_*
     commit_tally(t, I.cnt);
+}
+
+// Whether every generator range spans at most 64 source points (then the
+// LDS form keeps a segment's source rows in lanes): a range of kRangeCalls
+// calls starting at call c0 < C of its first point ends at most
+// (C - 1 + kRangeCalls - 1) / C points later.
+inline bool lane_rows_fit(const Inst &I)
+{
+    return ((uint64_t)I.C - 1 + kRangeCalls - 1) / I.C + 1 <= (uint64_t)kWave;
 }
 
 // Workgroups of the LDS form: one per compute unit (a block of up to
@@ -556,14 +747,16 @@ hipError_t launch_bucket_eval(const Inst &I, const BucketGeom &B, const PassASha
 {
     if (B.lds) {
         const size_t lds = ((size_t)1 << B.bshift) * (size_t)I.d * sizeof(float);
-        const bool buf = use_buffer(I);
+        const bool buf = use_buffer(I), lr = lane_rows_fit(I);
         return dispatch_small_d(I.d, [&]<int D>() -> hipError_t {
-            if (buf)
-                hipLaunchKernelGGL((k_bkt_eval_lds<D, true, kQ>), dim3(lds_eval_blocks()),
-                                   dim3(kLdsThreads), lds, st, I, B);
-            else
-                hipLaunchKernelGGL((k_bkt_eval_lds<D, false, kQ>), dim3(lds_eval_blocks()),
-                                   dim3(kLdsThreads), lds, st, I, B);
+#define SNG_LDS_LAUNCH(BUF, LR)                                                              \
+    hipLaunchKernelGGL((k_bkt_eval_lds<D, BUF, LR, kQ>), dim3(lds_eval_blocks()),             \
+                       dim3(kLdsThreads), lds, st, I, B)
+            if (buf && lr) SNG_LDS_LAUNCH(true, true);
+            else if (buf) SNG_LDS_LAUNCH(true, false);
+            else if (lr) SNG_LDS_LAUNCH(false, true);
+            else SNG_LDS_LAUNCH(false, false);
+#undef SNG_LDS_LAUNCH
             return hipGetLastError();
         });
     }

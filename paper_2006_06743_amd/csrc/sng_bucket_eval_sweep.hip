@@ -8,14 +8,16 @@ hipError_t launch_bucket_eval_sweep(const Inst &I, const SweepArgs &S, const Buc
 {
     if (B.lds) {
         const size_t lds = ((size_t)1 << B.bshift) * (size_t)I.d * sizeof(float);
-        const bool buf = use_buffer(I);
+        const bool buf = use_buffer(I), lr = lane_rows_fit(I);
         return dispatch_small_d(I.d, [&]<int D>() -> hipError_t {
-            if (buf)
-                hipLaunchKernelGGL((k_bkt_eval_lds_sweep<D, true>), dim3(lds_eval_blocks()),
-                                   dim3(kLdsThreads), lds, st, I, B, S);
-            else
-                hipLaunchKernelGGL((k_bkt_eval_lds_sweep<D, false>), dim3(lds_eval_blocks()),
-                                   dim3(kLdsThreads), lds, st, I, B, S);
+#define SNG_LDS_LAUNCH(BUF, LR)                                                              \
+    hipLaunchKernelGGL((k_bkt_eval_lds_sweep<D, BUF, LR>), dim3(lds_eval_blocks()),           \
+                       dim3(kLdsThreads), lds, st, I, B, S)
+            if (buf && lr) SNG_LDS_LAUNCH(true, true);
+            else if (buf) SNG_LDS_LAUNCH(true, false);
+            else if (lr) SNG_LDS_LAUNCH(false, true);
+            else SNG_LDS_LAUNCH(false, false);
+#undef SNG_LDS_LAUNCH
             return hipGetLastError();
         });
     }

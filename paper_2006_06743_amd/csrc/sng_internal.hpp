@@ -86,7 +86,10 @@ constexpr uint32_t kLdsBlockBytes = 128u << 10;
 struct BucketGeom {
     uint32_t bshift;     // partner block = 2^bshift rows
     uint32_t NJ;         // partner blocks
-    uint32_t lds;        // 1: blocks sized for LDS (rows of at most kLdsMaxD floats)
+    uint32_t lds;        // 1: blocks sized for LDS (rows of at most kLdsMaxD floats); records
+                         // then hold [partner offset: bshift bits][word: 2][call within
+                         // the point: tc_bits][source offset within the range: the rest]
+    uint32_t tc_bits;    // LDS records: bits of the call-within-point field
     uint64_t ranges;     // generator ranges
     uint64_t region;     // records per generator range (capacity)
     uint32_t *rec;       // [ranges][region] 4-byte slot records

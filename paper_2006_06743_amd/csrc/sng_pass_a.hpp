@@ -25,7 +25,6 @@ __device__ __forceinline__ void dot_step(float2 &acc, float a, float b)
 template <int D>
 struct SmallRow {
     static constexpr int kG = 1;
-    static constexpr int kD = D;
     static constexpr bool kPrefetch = true;
     struct Buf {
         float v[D];
