@@ -445,6 +445,7 @@ __device__ __forceinline__ void eval_ticket_lds(const Inst &I, const BucketGeom 
     const uint32_t jbase = J << B.bshift;
     const uint32_t pmask = (1u << B.bshift) - 1u;
     const uint32_t si_shift = B.bshift + 2 + B.tc_bits;
+    const auto *lblk = (const __attribute__((address_space(3))) float *)blk;
     const float *__restrict__ X = I.X;
     const int64_t ld = I.ld;
     const uint32_t ld4 = (uint32_t)ld * 4u;
@@ -492,8 +493,13 @@ __device__ __forceinline__ void eval_ticket_lds(const Inst &I, const BucketGeom 
 #pragma unroll
         for (int k = 0; k < P; ++k) {
             if constexpr (kLaneRows) {
-                const uint32_t r = w_src[k] + (uint32_t)lane;
-                nrow[k] = row_at(r < I.n ? r : I.n - 1u);
+                if constexpr (kBuf) {
+                    // rows past the last one read as zero through the buffer
+                    nrow[k] = Row::fetchb(rs, __umul24((uint32_t)lane, ld4) + w_src[k] * ld4, 0, D);
+                } else {
+                    const uint32_t r = w_src[k] + (uint32_t)lane;
+                    nrow[k] = row_at(r < I.n ? r : I.n - 1u);
+                }
             }
             nv[k] = __builtin_amdgcn_raw_buffer_load_b32(rrec, (int)((w_rec[k] + lane) * 4u), 0,
                                                         0);
@@ -523,6 +529,7 @@ __device__ __forceinline__ void eval_ticket_lds(const Inst &I, const BucketGeom 
         uint32_t ii[P], cj[P];
         bool live[P];
         Buf bi[P], bj[P];
+        bool bad = false;
 #pragma unroll
         for (int k = 0; k < P; ++k) {
             live[k] = (uint32_t)lane < c_n[k];
@@ -530,20 +537,26 @@ __device__ __forceinline__ void eval_ticket_lds(const Inst &I, const BucketGeom 
             ii[k] = c_src[k] + so;
             const uint32_t off = v[k] & pmask;
             cj[k] = jbase + off;
-            if (live[k] && !(ii[k] < I.n && cj[k] < I.n && (!kLaneRows || so < (uint32_t)kWave))) {
-                live[k] = false;  // never for a valid sample
-                atomicAdd(I.cnt + kCntOverflow, 1ull);
-            }
+            bad |= live[k] & ((ii[k] >= I.n) | (cj[k] >= I.n) | (kLaneRows & (so >= (uint32_t)kWave)));
             if constexpr (kLaneRows) {
+                // the permute reads lane so mod 64; a bad so is caught above
 #pragma unroll
                 for (int e = 0; e < D; ++e)
-                    bi[k].v[e] =
-                        __int_as_float(__shfl(__float_as_int(crow[k].v[e]), (int)(so & 63u)));
+                    bi[k].v[e] = __int_as_float(
+                        __builtin_amdgcn_ds_bpermute((int)(so << 2), __float_as_int(crow[k].v[e])));
             } else {
                 bi[k] = row_at(live[k] ? ii[k] : 0u);  // row 0 always exists
             }
-            // row 0 of the block is staged whenever the block exists
-            bj[k] = Row::fetch_lds(blk + (live[k] ? off : 0u) * (uint32_t)D);
+            // off < 2^bshift rows: inside the block's LDS whether staged or not
+            bj[k] = Row::fetch_lds(lblk + __umul24(off, (uint32_t)D));
+        }
+        if (__ballot(bad) != 0) {  // never for a valid sample
+            if (bad)
+                atomicAdd(I.cnt + kCntOverflow, 1ull);
+#pragma unroll
+            for (int k = 0; k < P; ++k)
+                live[k] = live[k] & ((ii[k] < I.n) & (cj[k] < I.n) &
+                                     (!kLaneRows | ((v[k] >> si_shift) < (uint32_t)kWave)));
         }
         float F[P], Q[P];
         bool act = false;

@@ -30,8 +30,9 @@ struct SmallRow {
         float v[D];
     };
     Buf r;
-    // A row staged in LDS as D packed floats.
-    __device__ __forceinline__ static Buf fetch_lds(const float *row)
+    // A row staged in LDS as D packed floats (an LDS address, so the
+    // address arithmetic stays 32-bit).
+    __device__ __forceinline__ static Buf fetch_lds(const __attribute__((address_space(3))) float *row)
     {
         Buf b;
 #pragma unroll
