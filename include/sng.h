@@ -149,7 +149,21 @@ typedef struct {
     uint64_t n_noise;
     uint64_t overflow;   /* non-zero: results invalid (a recheck queue overflowed, or a
                             reused partner-block sample was missing or damaged) */
-    double band_rel;     /* relative half-width of the recheck band used */
+    double band_rel;     /* relative half-width of the recheck band used: the binary32
+                            band around fl64(eps*eps) for the plain form; filter_rel_width
+                            for the mixed form (sng_dbscan_lowp) */
+    /* The mixed form's filter (sng_dbscan_lowp; zero after other calls). A pair is
+     * decided without the binary64 recheck only if eps lies outside
+     *   [T_lo - (r_i + r_j), T_hi + (r_i + r_j)],
+     * where [T_lo, T_hi] bounds the distance of the 16-bit copies given the binary32
+     * MFMA dot product (relative error filter_gamma on the products' magnitudes, plus
+     * the binary64 row statistics) and r_i = ||x_i - lp_scale * v_i|| is row i's
+     * rounding radius. */
+    double filter_gamma;     /* error bound of the binary32 accumulation: d*u/(1-d*u), u = 2^-22 */
+    double filter_r_max;     /* largest rounding radius r_i (rounded up) */
+    double filter_r_mean;    /* mean rounding radius */
+    double filter_rel_width; /* half-width of that interval relative to eps, for two rows of
+                                mean norm and mean radius at distance eps */
 } sng_stats;
 
 /* Human-readable name of a status code. Never NULL. */

@@ -59,6 +59,10 @@ class Stats:
     n_noise: int
     overflow: int
     band_rel: float
+    filter_gamma: float = 0.0
+    filter_r_max: float = 0.0
+    filter_r_mean: float = 0.0
+    filter_rel_width: float = 0.0
 
 
 def _stream(t: torch.Tensor) -> int:
@@ -110,7 +114,17 @@ def stats(ws: torch.Tensor, index: int = 0) -> Stats:
     if rc not in (_lib.SNG_OK, _lib.SNG_EOVERFLOW):
         check(rc, "sng_stats_read")
     return Stats(st.slots, st.self_pairs, st.accepted, st.rechecked, st.n_core, st.n_clusters,
-                 st.n_noise, st.overflow, st.band_rel)
+                 st.n_noise, st.overflow, st.band_rel, st.filter_gamma, st.filter_r_max,
+                 st.filter_r_mean, st.filter_rel_width)
+
+
+def lowp_bound(ws: torch.Tensor) -> dict:
+    """The mixed form's stated filter bound after a dbscan_lowp call on ws,
+    with the fraction of slots it sent to the binary64 recheck."""
+    st = stats(ws)
+    return {"filter_gamma": st.filter_gamma, "r_max": st.filter_r_max,
+            "r_mean": st.filter_r_mean, "rel_width_at_eps": st.filter_rel_width,
+            "recheck_fraction": st.rechecked / max(1, st.slots)}
 
 
 def degrees(X: torch.Tensor, m: int, eps: float, seed: int, cfg: Optional[Config] = None,

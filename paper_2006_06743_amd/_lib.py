@@ -42,7 +42,9 @@ class sng_stats(ctypes.Structure):
                 ("accepted", ctypes.c_uint64), ("rechecked", ctypes.c_uint64),
                 ("n_core", ctypes.c_uint64), ("n_clusters", ctypes.c_uint64),
                 ("n_noise", ctypes.c_uint64), ("overflow", ctypes.c_uint64),
-                ("band_rel", ctypes.c_double)]
+                ("band_rel", ctypes.c_double), ("filter_gamma", ctypes.c_double),
+                ("filter_r_max", ctypes.c_double), ("filter_r_mean", ctypes.c_double),
+                ("filter_rel_width", ctypes.c_double)]
 
 
 class SNGError(RuntimeError):

@@ -208,7 +208,7 @@ __device__ __forceinline__ void write_header(unsigned long long *cnt, unsigned l
                                              double band, int keep_sample)
 {
     const int t = threadIdx.x;
-    if (t < kCntNum)
+    if (t < kCntNum || (t > kCntNum && t < kFltEnd))
         cnt[t] = (t == kCntSlots) ? slots : 0ull;
     if (t == 0)
         ((double *)(cnt + kCntNum))[0] = band;
@@ -1211,7 +1211,7 @@ int sng_stats_read(const void *workspace, int32_t index, sng_stats *out, void *s
     hipStream_t st = (hipStream_t)stream;
     if (hipStreamSynchronize(st) != hipSuccess)
         return SNG_EHIP;
-    unsigned long long h[kCntNum + 1];
+    unsigned long long h[kFltEnd];
     const char *src = (const char *)workspace + (size_t)index * kInstHeader;
     if (hipMemcpy(h, src, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess)
         return SNG_EHIP;
@@ -1224,6 +1224,27 @@ int sng_stats_read(const void *workspace, int32_t index, sng_stats *out, void *s
     out->n_noise = h[kCntNoise];
     out->overflow = h[kCntOverflow];
     memcpy(&out->band_rel, &h[kCntNum], sizeof(double));
+    out->filter_gamma = out->filter_r_max = out->filter_r_mean = out->filter_rel_width = 0.0;
+    double f[kFltEnd - kFltGamma];
+    memcpy(f, &h[kFltGamma], sizeof(f));
+    const uint64_t rows = h[kFltRows];
+    if (f[0] > 0.0 && rows > 0) {  // a mixed-form call: derive its filter's width
+        const double gamma = f[0], gamma_norm = f[kFltGammaNorm - kFltGamma];
+        const double scale2 = f[kFltScale2 - kFltGamma], eps2 = f[kFltEps2 - kFltGamma];
+        const double r_mean = f[kFltRSum - kFltGamma] / (double)rows;
+        const double a_mean = f[kFltASum - kFltGamma] / (double)rows;
+        out->filter_gamma = gamma;
+        out->filter_r_max = f[kFltRMax - kFltGamma];
+        out->filter_r_mean = r_mean;
+        // two rows of norm a and radius r at distance eps: the copy's squared
+        // distance is known within scale^2 * 2a^2 (gamma + gamma_norm), i.e. its
+        // distance within half that over eps, and the rows within 2r of the copies
+        const double eps = sqrt(eps2);
+        out->filter_rel_width =
+            eps > 0.0 ? (2.0 * r_mean + scale2 * a_mean * a_mean * (gamma + gamma_norm) / eps) / eps
+                      : HUGE_VAL;
+        out->band_rel = out->filter_rel_width;
+    }
     return out->overflow ? SNG_EOVERFLOW : SNG_OK;
 }
 

@@ -40,7 +40,7 @@ __global__ __launch_bounds__(256) void k_b_init(const Inst *__restrict__ T, cons
     const int k = block_instance(G.pblk, G.count, blockIdx.x);
     const Inst &I = T[k];
     const uint64_t b = blockIdx.x - G.pblk[k];
-    if (b == 0 && threadIdx.x < kCntNum)
+    if (b == 0 && (threadIdx.x < kCntNum || (threadIdx.x > kCntNum && threadIdx.x < kFltEnd)))
         I.cnt[threadIdx.x] = (threadIdx.x == kCntSlots) ? (unsigned long long)I.n * I.m : 0ull;
     if (b == 0 && threadIdx.x == 0)
         reinterpret_cast<double *>(I.cnt)[kCntNum] = I.band;

@@ -25,6 +25,21 @@ enum Counter : int {
     kCntQueue = 8,
     kCntNum = 16
 };
+// Header words of the mixed form's filter (doubles unless noted), cleared
+// with the counters: its error constants, then max and sum of the rows'
+// rounding radii and norms.
+enum {
+    kFltGamma = 17,
+    kFltGammaNorm = 18,
+    kFltScale2 = 19,
+    kFltEps2 = 20,
+    kFltRMax = 21,
+    kFltAMax = 22,
+    kFltRSum = 23,
+    kFltASum = 24,
+    kFltRows = 25,  // u64
+    kFltEnd = 26
+};
 
 // Similarity queries other than the distance: an edge when the dot product
 // (kSimDot) or the cosine (kSimCos) of the pair is at least tau; binary64 in

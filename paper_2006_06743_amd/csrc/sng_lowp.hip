@@ -63,11 +63,57 @@ __global__ __launch_bounds__(256) void k_rowstats(Inst I, LowpArgs L)
         }
         if (lane == 0) {
             const double nvu = nv * up;
+            const double a = __builtin_sqrt(nvu) * (1.0 + 0x1p-40);
+            const double r = __builtin_sqrt(rr * up) * (1.0 + 0x1p-40);
             L.stats[4 * i + 0] = nvu;
-            L.stats[4 * i + 1] = __builtin_sqrt(nvu) * (1.0 + 0x1p-40);
-            L.stats[4 * i + 2] = __builtin_sqrt(rr * up) * (1.0 + 0x1p-40);
+            L.stats[4 * i + 1] = a;
+            L.stats[4 * i + 2] = r;
             L.stats[4 * i + 3] = 0.0;
         }
+    }
+}
+
+// The filter's reported bound (not used by any decision): its constants, and
+// the largest and summed rounding radii and row norms, reduced by one
+// workgroup in a fixed order.
+constexpr int kSummaryThreads = 1024;
+__global__ __launch_bounds__(kSummaryThreads) void k_rowstats_summary(Inst I, LowpArgs L)
+{
+    __shared__ double red[4][kSummaryThreads];
+    const int t = threadIdx.x;
+    double rmax = 0.0, amax = 0.0, rsum = 0.0, asum = 0.0;
+    for (uint64_t i = t; i < I.n; i += kSummaryThreads) {
+        const double a = L.stats[4 * i + 1], r = L.stats[4 * i + 2];
+        rmax = r > rmax ? r : rmax;
+        amax = a > amax ? a : amax;
+        rsum += r;
+        asum += a;
+    }
+    red[0][t] = rmax;
+    red[1][t] = amax;
+    red[2][t] = rsum;
+    red[3][t] = asum;
+    __syncthreads();
+    for (int w = kSummaryThreads / 2; w > 0; w >>= 1) {
+        if (t < w) {
+            red[0][t] = red[0][t + w] > red[0][t] ? red[0][t + w] : red[0][t];
+            red[1][t] = red[1][t + w] > red[1][t] ? red[1][t + w] : red[1][t];
+            red[2][t] += red[2][t + w];
+            red[3][t] += red[3][t + w];
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        double *h = reinterpret_cast<double *>(I.cnt);
+        h[kFltGamma] = L.gamma_acc;
+        h[kFltGammaNorm] = L.gamma_norm;
+        h[kFltScale2] = L.scale2;
+        h[kFltEps2] = I.eps2;
+        h[kFltRMax] = red[0][0];
+        h[kFltAMax] = red[1][0];
+        h[kFltRSum] = red[2][0];
+        h[kFltASum] = red[3][0];
+        I.cnt[kFltRows] = I.n;
     }
 }
 
@@ -346,6 +392,9 @@ hipError_t launch_lowp(const Inst &I, const LowpArgs &L, int prec, hipStream_t s
         hipLaunchKernelGGL(k_rowstats<2>, dim3(stat_blocks), dim3(256), 0, st, I, L);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(k_rowstats_summary, dim3(1), dim3(kSummaryThreads), 0, st, I, L);
+    if ((e = hipGetLastError()) != hipSuccess)
         return e;
     const uint64_t nb = ((uint64_t)I.n + waves - 1) / waves;
     const unsigned blocks = (unsigned)(nb < 8192 ? nb : 8192);

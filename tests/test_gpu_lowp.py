@@ -165,3 +165,72 @@ def test_out_degree_mode_lowp(sng, orc, prec):
     torch.cuda.synchronize()
     ref = orc.dbscan(X, 0.4, 3, seed, s=0.05, out_degree=True)
     assert_same(lab.cpu().numpy(), deg.cpu().numpy().view(np.uint32), ref, "lowp out-degree")
+
+
+def _decode(bits, prec):
+    b = np.ascontiguousarray(bits, dtype=np.uint16)
+    if prec == 1:
+        return (b.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+    return b.view(np.float16).astype(np.float64)
+
+
+@pytest.mark.parametrize("prec", [1, 2], ids=["bf16", "fp16"])
+def test_filter_bound_is_reported_and_respected(sng, orc, prec):
+    """The mixed form reports its filter: the accumulation bound, the rows'
+    rounding radii r_i = ||x_i - scale v_i|| and the relative width at eps.
+    On points at distance eps from a cluster centre, every slot whose copy
+    distance T lies within r_i + r_j of eps must have been rechecked (then
+    neither side of eps can be certain), and no slot outside the interval
+    that the stated accumulation bound allows may have been."""
+    import torch
+    rng = np.random.default_rng(32 + prec)
+    d, eps, s, seed, scale = 48, 0.8, 0.1, 8, 1.0
+    u = rng.normal(size=(1200, d))
+    u /= np.linalg.norm(u, axis=1, keepdims=True)
+    X = np.vstack([rng.normal(0, 0.01, size=(200, d)), eps * u]).astype(np.float32)
+    n = X.shape[0]
+    bits = bits_for(X, prec, scale)
+    Xg = torch.from_numpy(np.ascontiguousarray(X)).cuda()
+    lab, deg, ws = sng.dbscan_lowp(Xg, lp_tensor(bits), s, eps, 3, seed, prec=prec,
+                                   lp_scale=scale)
+    torch.cuda.synchronize()
+    st = sng.stats(ws)
+    ref = orc.dbscan(X, eps, 3, seed, s=s)
+    assert_same(lab.cpu().numpy(), deg.cpu().numpy().view(np.uint32), ref, "sphere")
+    # the stated constants, recomputed from the rows
+    v = _decode(bits, prec)
+    x = X.astype(np.float64)
+    r = np.sqrt(((x - scale * v) ** 2).sum(1))
+    a = np.sqrt((v ** 2).sum(1))
+    u22 = 2.0 ** -22
+    gamma = d * u22 / (1 - d * u22)
+    gamma_norm = (2.0 * d + 24.0) * 2.0 ** -52
+    assert st.filter_gamma == gamma
+    assert r.max() * (1 - 1e-12) <= st.filter_r_max <= r.max() * (1 + 1e-9) + 1e-300
+    assert abs(st.filter_r_mean - r.mean()) <= 1e-9 * r.mean() + 1e-300
+    width = (2 * r.mean() + scale ** 2 * a.mean() ** 2 * (gamma + gamma_norm) / eps) / eps
+    assert abs(st.filter_rel_width - width) <= 1e-6 * width
+    assert st.band_rel == st.filter_rel_width
+    # every slot: the copy's distance T and the interval the filter leaves open
+    m = orc.samples_per_point(s, n)
+    I = np.repeat(np.arange(n), m)
+    J = np.array([orc.partner(seed, n, i, t) for i in range(n) for t in range(m)], np.int64)
+    keep = I != J
+    I, J = I[keep], J[keep]
+    E = ((v[I] - v[J]) ** 2).sum(1)
+    T = scale * np.sqrt(E)
+    R = r[I] + r[J]
+    delta = gamma * 2 * a[I] * a[J] + gamma_norm * (a[I] ** 2 + a[J] ** 2)
+    t_lo = scale * np.sqrt(np.maximum(E - 2 * delta, 0.0))
+    t_hi = scale * np.sqrt(E + 2 * delta)
+    must = np.abs(T - eps) < R - 1e-9 * eps
+    may = (t_lo - R <= eps * (1 + 1e-9)) & (t_hi + R >= eps * (1 - 1e-9))
+    print("prec %d: must %d <= rechecked %d <= may %d of %d slots"
+          % (prec, must.sum(), st.rechecked, may.sum(), I.size), flush=True)
+    assert must.sum() > 0
+    assert must.sum() <= st.rechecked <= may.sum()
+    # the plain form reports no filter
+    lab2, deg2, ws2 = sng.dbscan(Xg, s, eps, 3, seed)
+    torch.cuda.synchronize()
+    st2 = sng.stats(ws2)
+    assert st2.filter_gamma == 0.0 and st2.filter_rel_width == 0.0
