@@ -61,6 +61,15 @@ def load() -> ctypes.CDLL:
     return lib
 
 
+def set_threads(n: int) -> int:
+    """Sets the oracle's OpenMP thread count (omp_set_num_threads of the
+    OpenMP runtime it links) and returns omp_get_max_threads() after it."""
+    load()
+    gomp = ctypes.CDLL("libgomp.so.1")
+    gomp.omp_set_num_threads(ctypes.c_int(int(n)))
+    return int(gomp.omp_get_max_threads())
+
+
 def _ptr(a: Optional[np.ndarray]):
     return None if a is None else a.ctypes.data
 
