@@ -406,21 +406,23 @@ constexpr int kLdsWindows = 4;  // windows decided per iteration of a wavefront
 static_assert(kLdsTicketRanges <= kWave, "one lane per segment of a ticket");
 
 // One ticket of the LDS form: the records of partner block J from T <= 64
-// consecutive ranges (segments), one lane per pair. The wavefront walks the
-// segments in order in windows of up to 64 records of one segment (a
-// segment holds about kRangeCalls*4/NJ records, so most take one window),
-// so a window's record base and first source are scalars. It decides P
-// windows per iteration and loads the next P windows' records (and source
-// rows) before deciding the current ones, to keep loads in flight. The
-// partner row is read from `blk`, the staged block. Records carry the
-// source's offset within its range and the call within the point as bit
-// fields (BucketGeom::lds), so a source index is one add.
-// kLaneRows (every range spans at most 64 sources): lane k holds source row
-// i0 + k of a window's segment, loaded with one coalesced load, and each
-// lane takes its source row from there by a cross-lane permute; otherwise
-// each lane loads its source row. Every record is filtered in binary32
-// first, and the decision and bookkeeping run only when some lane may accept
-// or must recheck, so windows of rejections cost the filter alone.
+// consecutive ranges (segments), one lane per pair. Each segment is cut into
+// windows of up to 64 records (a segment holds about kRangeCalls*4/NJ
+// records, so most take one window), and a window's record base, first
+// source and record count are scalars. A table of up to 64 windows sits one
+// window per lane (each lane finds its segment by a binary search over the
+// segments' window prefix); the wavefront decides P windows per iteration,
+// reading their entries with readlane, and loads the next P windows' records
+// (and source rows) before deciding the current ones. The partner row is
+// read from `blk`, the staged block. Records carry the source's offset within
+// its range and the call within the point as bit fields (BucketGeom::lds),
+// so a source index is one add. kLaneRows (every range spans at most 64
+// sources): lane k holds source row i0 + k of a window's segment, loaded
+// with one coalesced load, and each lane takes its source row from there by
+// a cross-lane permute; otherwise each lane loads its source row. Every
+// record is filtered in binary32 first, and the decision and bookkeeping run
+// only when some lane may accept or must recheck, so windows of rejections
+// cost the filter alone.
 template <int D, int P, bool kBuf, bool kLaneRows, class Pol>
 __device__ __forceinline__ void eval_ticket_lds(const Inst &I, const BucketGeom &B, Pol &pol,
                                                 uint64_t r0, uint32_t T, uint32_t J,
@@ -438,9 +440,19 @@ __device__ __forceinline__ void eval_ticket_lds(const Inst &I, const BucketGeom 
         cnt_l = B.seg[(r * B.NJ + J) * 2 + 1];
         i0_l = B.start[2 * r + 0];
     }
-    uint64_t nonempty = __ballot(cnt_l > 0);  // segments not yet entered
-    if (nonempty == 0)
+    // windows of each segment and their inclusive prefix over the segments
+    const uint32_t wc_l = (cnt_l + (uint32_t)kWave - 1) / (uint32_t)kWave;
+    uint32_t winc = wc_l;
+#pragma unroll
+    for (int s = 1; s < kWave; s <<= 1) {
+        const uint32_t u = __shfl_up(winc, s);
+        if (lane >= s)
+            winc += u;
+    }
+    const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)winc, kWave - 1);
+    if (total == 0)
         return;  // wave-uniform
+    const uint32_t wexcl_l = winc - wc_l;
 
     const uint32_t jbase = J << B.bshift;
     const uint32_t pmask = (1u << B.bshift) - 1u;
@@ -459,33 +471,39 @@ __device__ __forceinline__ void eval_ticket_lds(const Inst &I, const BucketGeom 
             return Row::fetch(X + (int64_t)r * ld, 0, D);
     };
 
-    // scalar walker: the current segment (count, record base, first source)
-    // and offset o; `left` false once every window has been handed out
-    uint32_t cnt = 0, base = 0, src = 0, o = 0;
-    bool left = true;
-    auto enter = [&]() {
-        const int sg = __builtin_ctzll(nonempty);
-        nonempty &= nonempty - 1;
-        cnt = (uint32_t)__builtin_amdgcn_readlane((int)cnt_l, sg);
-        base = (uint32_t)__builtin_amdgcn_readlane((int)base_l, sg);
-        src = (uint32_t)__builtin_amdgcn_readlane((int)i0_l, sg);
-        o = 0;
+    // the window table of windows [wb, wb + 64): lane w holds window wb + w
+    uint32_t t_rec = 0, t_src = 0, t_n = 0;
+    auto build = [&](uint32_t wb) {
+        const uint32_t w = wb + (uint32_t)lane;
+        // its segment: the first l with winc_l > w (winc is non-decreasing)
+        uint32_t sg = 0;
+#pragma unroll
+        for (uint32_t step = 32; step > 0; step >>= 1) {
+            const uint32_t e = (uint32_t)__builtin_amdgcn_ds_bpermute(
+                (int)((sg + step - 1) << 2), (int)winc);
+            sg += (e <= w) ? step : 0u;
+        }
+        sg &= 63u;
+        const uint32_t a = sg << 2;
+        const uint32_t o = (w - (uint32_t)__builtin_amdgcn_ds_bpermute((int)a, (int)wexcl_l)) *
+                           (uint32_t)kWave;
+        const uint32_t c = (uint32_t)__builtin_amdgcn_ds_bpermute((int)a, (int)cnt_l);
+        t_rec = (uint32_t)__builtin_amdgcn_ds_bpermute((int)a, (int)base_l) + o;
+        t_src = (uint32_t)__builtin_amdgcn_ds_bpermute((int)a, (int)i0_l);
+        t_n = (w < total && c > o) ? min(c - o, (uint32_t)kWave) : 0u;
     };
-    enter();
-    // a window: its first record, source and record count (0: none)
+    // window k's entries (k in the current table)
+    uint32_t wb = 0;
+    build(0);
     uint32_t w_rec[P], w_src[P], w_n[P];
-    auto take = [&](int k) {
-        w_rec[k] = base + o;
-        w_src[k] = src;
-        w_n[k] = left ? min(cnt - o, (uint32_t)kWave) : 0u;
-        if (!left)
-            return;
-        if (o + kWave < cnt)
-            o += kWave;
-        else if (nonempty != 0)
-            enter();
-        else
-            left = false;
+    auto take = [&](uint32_t k0) {
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            const int at = (int)(k0 + (uint32_t)k - wb);  // < 64 (tables are rebuilt first)
+            w_rec[k] = (uint32_t)__builtin_amdgcn_readlane((int)t_rec, at);
+            w_src[k] = (uint32_t)__builtin_amdgcn_readlane((int)t_src, at);
+            w_n[k] = (uint32_t)__builtin_amdgcn_readlane((int)t_n, at);
+        }
     };
     uint32_t nv[P];
     Buf nrow[P];
@@ -505,11 +523,10 @@ __device__ __forceinline__ void eval_ticket_lds(const Inst &I, const BucketGeom 
                                                         0);
         }
     };
-#pragma unroll
-    for (int k = 0; k < P; ++k)
-        take(k);
+    static_assert(kWave % P == 0, "windows per iteration divide the table");
+    take(0);
     issue();
-    for (;;) {  // wave-uniform
+    for (uint32_t k0 = 0; k0 < total; k0 += P) {  // wave-uniform
         uint32_t v[P], c_src[P], c_n[P];
         Buf crow[P];
 #pragma unroll
@@ -519,11 +536,19 @@ __device__ __forceinline__ void eval_ticket_lds(const Inst &I, const BucketGeom 
             c_src[k] = w_src[k];
             c_n[k] = w_n[k];
         }
-        if (c_n[0] == 0)
-            break;  // nothing was handed out
+        // the next P windows (a new table every 64 windows; windows past the
+        // last have no records and load harmlessly)
+        const uint32_t k1 = k0 + P;
+        if (k1 - wb >= (uint32_t)kWave && k1 < total) {
+            wb = k1;
+            build(wb);
+        }
+        take(k1 < total ? k1 : wb);
+        if (k1 >= total) {
 #pragma unroll
-        for (int k = 0; k < P; ++k)
-            take(k);
+            for (int k = 0; k < P; ++k)
+                w_n[k] = 0;
+        }
         issue();  // the next P windows load while these are decided
 
         uint32_t ii[P], cj[P];
