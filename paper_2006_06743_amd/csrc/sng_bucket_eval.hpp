@@ -416,10 +416,11 @@ static_assert(kLdsTicketRanges <= kWave, "one lane per segment of a ticket");
 // (and source rows) before deciding the current ones. The partner row is
 // read from `blk`, the staged block. Records carry the source's offset within
 // its range and the call within the point as bit fields (BucketGeom::lds),
-// so a source index is one add. kLaneRows (every range spans at most 64
-// sources): lane k holds source row i0 + k of a window's segment, loaded
-// with one coalesced load, and each lane takes its source row from there by
-// a cross-lane permute; otherwise each lane loads its source row. Every
+// so a source index is one add. kLaneRows (the rows of every range's
+// sources hold at most 64 elements): lane t holds element t mod D of source
+// row i0 + t / D of a window's segment, loaded with one coalesced dword load,
+// and each lane takes its source row from there by D cross-lane permutes;
+// otherwise each lane loads its source row. Every
 // record is filtered in binary32 first, and the decision and bookkeeping run
 // only when some lane may accept or must recheck, so windows of rejections
 // cost the filter alone.
@@ -505,18 +506,22 @@ __device__ __forceinline__ void eval_ticket_lds(const Inst &I, const BucketGeom 
             w_n[k] = (uint32_t)__builtin_amdgcn_readlane((int)t_n, at);
         }
     };
+    // kLaneRows: lane t holds element t mod D of source row src + t / D
+    // (rows src .. src + 64/D - 1 cover every source of a range)
+    const uint32_t lr_row = (uint32_t)lane / (uint32_t)D;
+    const uint32_t lr_el = (uint32_t)lane - lr_row * (uint32_t)D;
     uint32_t nv[P];
-    Buf nrow[P];
+    float nrow[P];
     auto issue = [&]() {  // loads of the windows in w_* (harmless ones for empty windows)
 #pragma unroll
         for (int k = 0; k < P; ++k) {
             if constexpr (kLaneRows) {
+                const uint32_t r = w_src[k] + lr_row;
                 if constexpr (kBuf) {
                     // rows past the last one read as zero through the buffer
-                    nrow[k] = Row::fetchb(rs, __umul24((uint32_t)lane, ld4) + w_src[k] * ld4, 0, D);
+                    nrow[k] = bld1(rs, __umul24(lr_row, ld4) + w_src[k] * ld4 + lr_el * 4u);
                 } else {
-                    const uint32_t r = w_src[k] + (uint32_t)lane;
-                    nrow[k] = row_at(r < I.n ? r : I.n - 1u);
+                    nrow[k] = X[(int64_t)(r < I.n ? r : I.n - 1u) * ld + lr_el];
                 }
             }
             nv[k] = __builtin_amdgcn_raw_buffer_load_b32(rrec, (int)((w_rec[k] + lane) * 4u), 0,
@@ -528,7 +533,7 @@ __device__ __forceinline__ void eval_ticket_lds(const Inst &I, const BucketGeom 
     issue();
     for (uint32_t k0 = 0; k0 < total; k0 += P) {  // wave-uniform
         uint32_t v[P], c_src[P], c_n[P];
-        Buf crow[P];
+        float crow[P];
 #pragma unroll
         for (int k = 0; k < P; ++k) {
             v[k] = nv[k];
@@ -562,13 +567,15 @@ __device__ __forceinline__ void eval_ticket_lds(const Inst &I, const BucketGeom 
             ii[k] = c_src[k] + so;
             const uint32_t off = v[k] & pmask;
             cj[k] = jbase + off;
-            bad |= live[k] & ((ii[k] >= I.n) | (cj[k] >= I.n) | (kLaneRows & (so >= (uint32_t)kWave)));
+            bad |= live[k] & ((ii[k] >= I.n) | (cj[k] >= I.n) |
+                              (kLaneRows & (so >= (uint32_t)(kWave / D))));
             if constexpr (kLaneRows) {
-                // the permute reads lane so mod 64; a bad so is caught above
+                // the permutes read lanes so*D + e mod 64; a bad so is caught above
+                const uint32_t a = __umul24(so, 4u * (uint32_t)D);
 #pragma unroll
                 for (int e = 0; e < D; ++e)
                     bi[k].v[e] = __int_as_float(
-                        __builtin_amdgcn_ds_bpermute((int)(so << 2), __float_as_int(crow[k].v[e])));
+                        __builtin_amdgcn_ds_bpermute((int)(a + 4u * e), __float_as_int(crow[k])));
             } else {
                 bi[k] = row_at(live[k] ? ii[k] : 0u);  // row 0 always exists
             }
@@ -581,7 +588,7 @@ __device__ __forceinline__ void eval_ticket_lds(const Inst &I, const BucketGeom 
 #pragma unroll
             for (int k = 0; k < P; ++k)
                 live[k] = live[k] & ((ii[k] < I.n) & (cj[k] < I.n) &
-                                     (!kLaneRows | ((v[k] >> si_shift) < (uint32_t)kWave)));
+                                     (!kLaneRows | ((v[k] >> si_shift) < (uint32_t)(kWave / D))));
         }
         float F[P], Q[P];
         bool act = false;
@@ -717,13 +724,13 @@ __global__ __launch_bounds__(kLdsThreads) void k_bkt_eval_lds_sweep(Inst I, Buck
     commit_tally(t, I.cnt);
 }
 
-// Whether every generator range spans at most 64 source points (then the
-// LDS form keeps a segment's source rows in lanes): a range of kRangeCalls
-// calls starting at call c0 < C of its first point ends at most
+// Whether the source rows of every generator range fit one element per lane
+// (then the LDS form keeps a segment's source rows in lanes): a range of
+// kRangeCalls calls starting at call c0 < C of its first point ends at most
 // (C - 1 + kRangeCalls - 1) / C points later.
 inline bool lane_rows_fit(const Inst &I)
 {
-    return ((uint64_t)I.C - 1 + kRangeCalls - 1) / I.C + 1 <= (uint64_t)kWave;
+    return (((uint64_t)I.C - 1 + kRangeCalls - 1) / I.C + 1) * (uint64_t)I.d <= (uint64_t)kWave;
 }
 
 // Workgroups of the LDS form: one per compute unit (a block of up to
