@@ -66,14 +66,18 @@ __device__ __forceinline__ uint32_t gen_exclusive(uint32_t v, uint32_t *wsum, ui
     return before + x - v;
 }
 
-template <bool kF32Mod>
+// kMod: 0 the binary64 remainder, 1 the binary32 one, 2 the binary32 one
+// with a 24-bit multiply (n < 2^24).
+template <int kMod>
 __global__ __launch_bounds__(kGenThreads) void k_bkt_generate(Inst I, BucketGeom B)
 {
     extern __shared__ uint32_t lds_u32[];
     __shared__ uint32_t wsum[kGenThreads / kWave];
-    uint32_t *stage = lds_u32;              // [kRangeSlots]
-    uint32_t *cnt = lds_u32 + kRangeSlots;  // [NJ]
-    uint32_t *pre = cnt + B.NJ;             // [NJ]
+    // counts and offsets per partner block first, so that their LDS
+    // addresses are small constants plus the block index
+    uint32_t *cnt = lds_u32;               // [NJ]
+    uint32_t *pre = cnt + B.NJ;            // [NJ]
+    uint32_t *stage = pre + B.NJ;          // [kRangeSlots]
     const uint32_t tid = threadIdx.x;
     const uint64_t r = blockIdx.x;
     const uint64_t call_lo = r * kRangeCalls;
@@ -87,6 +91,18 @@ __global__ __launch_bounds__(kGenThreads) void k_bkt_generate(Inst I, BucketGeom
         B.start[2 * r + 1] = c0;
     }
     __syncthreads();
+    // this thread's calls are c0 + tid + k * kGenThreads of the range: the
+    // first split into (source, call within the point) by one division, the
+    // next ones advanced by kGenThreads = step_q * C + step_r calls
+    uint32_t cc = c0 + tid, ii = i0;
+    if (cc >= I.C) {
+        const uint32_t q = div_exact(cc, I.C, I.inv_C);
+        ii += q;
+        cc -= q * I.C;
+    }
+    const uint32_t step_q = kGenThreads / I.C;
+    const uint32_t step_r = kGenThreads - step_q * I.C;
+    const uint32_t pmask = (1u << B.bshift) - 1u;
     // key: partner block << 16 | rank of the record within its block
     uint32_t key[4 * kCallsPerThread], rec[4 * kCallsPerThread];
     uint32_t self = 0;
@@ -94,33 +110,35 @@ __global__ __launch_bounds__(kGenThreads) void k_bkt_generate(Inst I, BucketGeom
     for (uint32_t c = 0; c < kCallsPerThread; ++c) {
         const uint32_t off = c * kGenThreads + tid;
         const bool live = call_lo + off < call_hi;
-        uint32_t cc = c0 + off, ii = i0;
-        if (cc >= I.C) {
-            const uint32_t q = div_exact(cc, I.C, I.inv_C);
-            ii += q;
-            cc -= q * I.C;
-        }
         const uint32_t nvalid = live ? min(4u, I.m - 4u * cc) : 0u;
         const Words4 W = philox10(cc, ii, I.key0, I.key1);
+        // the record's fields other than the partner and its word
+        const uint32_t hi_bits = B.lds ? (((ii - i0) << B.tc_bits) | cc) << (B.bshift + 2)
+                                       : (off << kRecOffShift);
+        const uint32_t w_shift = B.lds ? B.bshift : 16u;
 #pragma unroll
         for (int w = 0; w < 4; ++w) {
             uint32_t kk = ~0u, rr = 0;
             if ((uint32_t)w < nvalid) {
-                const uint32_t j = kF32Mod ? mod_f32(W.w[w], I.n, I.inv_nf)
-                                           : mod_exact(W.w[w], I.n, I.inv_n);
+                const uint32_t j = kMod == 2   ? mod_f32_n24(W.w[w], I.n, I.inv_nf)
+                                   : kMod == 1 ? mod_f32(W.w[w], I.n, I.inv_nf)
+                                               : mod_exact(W.w[w], I.n, I.inv_n);
                 if (j == ii) {
                     ++self;
                 } else {
                     const uint32_t J = j >> B.bshift;
                     kk = (J << 16) | atomicAdd(cnt + J, 1u);
-                    const uint32_t pj = j & ((1u << B.bshift) - 1u);
-                    rr = B.lds ? ((((ii - i0) << B.tc_bits) | cc) << (B.bshift + 2)) |
-                                     ((uint32_t)w << B.bshift) | pj
-                               : (off << kRecOffShift) | ((uint32_t)w << 16) | pj;
+                    rr = hi_bits | ((uint32_t)w << w_shift) | (j & pmask);
                 }
             }
             key[4 * c + w] = kk;
             rec[4 * c + w] = rr;
+        }
+        cc += step_r;
+        ii += step_q;
+        if (cc >= I.C) {
+            cc -= I.C;
+            ++ii;
         }
     }
     __syncthreads();
@@ -140,13 +158,20 @@ __global__ __launch_bounds__(kGenThreads) void k_bkt_generate(Inst I, BucketGeom
     }
     __syncthreads();
     uint32_t *dst = B.rec + r * B.region;
-    for (uint32_t k = 4 * tid; k < total; k += 4 * kGenThreads) {
-        if (k + 4 <= total) {
-            *reinterpret_cast<uint4 *>(dst + k) = *reinterpret_cast<const uint4 *>(stage + k);
-        } else {
-            for (uint32_t e = k; e < total; ++e)
-                dst[e] = stage[e];
+    // stage starts 2*NJ words into LDS: copy out in 16-byte pieces when that
+    // keeps both sides aligned, else word by word
+    if ((B.NJ & 1u) == 0) {
+        for (uint32_t k = 4 * tid; k < total; k += 4 * kGenThreads) {
+            if (k + 4 <= total) {
+                *reinterpret_cast<uint4 *>(dst + k) = *reinterpret_cast<const uint4 *>(stage + k);
+            } else {
+                for (uint32_t e = k; e < total; ++e)
+                    dst[e] = stage[e];
+            }
         }
+    } else {
+        for (uint32_t k = tid; k < total; k += kGenThreads)
+            dst[k] = stage[k];
     }
     const int slots[1] = {1};
     const uint32_t sv[1] = {self};
@@ -273,11 +298,14 @@ hipError_t launch_bucket_generate(const Inst &I, const BucketGeom &B, hipStream_
         return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_bkt_prepare, dim3(1), dim3(64), 0, st, B, 1);
     const size_t lds = ((size_t)kRangeSlots + 2 * (size_t)B.NJ) * sizeof(uint32_t);
-    if (I.inv_nf != 0.0f)
-        hipLaunchKernelGGL(k_bkt_generate<true>, dim3((unsigned)B.ranges), dim3(kGenThreads), lds,
+    if (I.inv_nf != 0.0f && I.n < (1u << 24))
+        hipLaunchKernelGGL(k_bkt_generate<2>, dim3((unsigned)B.ranges), dim3(kGenThreads), lds,
+                           st, I, B);
+    else if (I.inv_nf != 0.0f)
+        hipLaunchKernelGGL(k_bkt_generate<1>, dim3((unsigned)B.ranges), dim3(kGenThreads), lds,
                            st, I, B);
     else
-        hipLaunchKernelGGL(k_bkt_generate<false>, dim3((unsigned)B.ranges), dim3(kGenThreads), lds,
+        hipLaunchKernelGGL(k_bkt_generate<0>, dim3((unsigned)B.ranges), dim3(kGenThreads), lds,
                            st, I, B);
     hipLaunchKernelGGL(k_bkt_seal, dim3(1), dim3(64), 0, st, B);
     return hipGetLastError();

@@ -176,6 +176,16 @@ __device__ __forceinline__ uint32_t mod_f32(uint32_t w, uint32_t n, float inv)
     return min(min(r, r + n), r - n);
 }
 
+// The same for n < 2^24: the quotient estimate is below 2^32 / 1024 = 2^22,
+// so q * n is a 24-bit multiply (full rate) whose low 32 bits are all the
+// remainder needs.
+__device__ __forceinline__ uint32_t mod_f32_n24(uint32_t w, uint32_t n, float inv)
+{
+    const uint32_t q = (uint32_t)((float)w * inv);
+    const uint32_t r = w - __umul24(q, n);
+    return min(min(r, r + n), r - n);
+}
+
 // The four partners of one Philox call: its words mod n. The branch is
 // uniform (one instance per wavefront), so only one side runs.
 __device__ __forceinline__ void partners4(const Inst &I, const Words4 &W, uint32_t j[4])
