@@ -21,6 +21,7 @@
 //
 // Decisions are the plain path's (binary32 band, binary64 recheck), so
 // degrees, accept bits and labels are identical to the direct schedule.
+#include <math.h>
 #include <string.h>
 
 #include "sng_bucket_eval.hpp"
@@ -29,8 +30,8 @@ namespace sng {
 
 
 // ---------------------------------------------------------------------------
-// Generate. LDS: the record stage of the range, then counts and offsets per
-// partner block.
+// Generate. LDS: a count and an offset per partner block, then the record
+// stage of the range.
 // ---------------------------------------------------------------------------
 constexpr uint32_t kGenThreads = 1024;
 constexpr uint32_t kCallsPerThread = (uint32_t)kRangeCalls / kGenThreads;
@@ -40,7 +41,9 @@ static_assert(kRangeCalls <= (1u << (32 - kRecOffShift)), "call offset field");
 static_assert(kMaxPartnerBlocks <= kGenThreads, "one count per thread in the prefix");
 
 // Exclusive prefix of v over a workgroup of kGenThreads threads; *total gets
-// the sum. wsum: kGenThreads / kWave words of LDS.
+// the sum. Each wavefront scans its values, wavefront 0 then scans the
+// wavefront totals. wsum: 2 * kGenWaves + 1 words of LDS.
+constexpr int kGenWaves = (int)(kGenThreads / kWave);
 __device__ __forceinline__ uint32_t gen_exclusive(uint32_t v, uint32_t *wsum, uint32_t *total)
 {
     const int lane = lane_id();
@@ -55,37 +58,55 @@ __device__ __forceinline__ uint32_t gen_exclusive(uint32_t v, uint32_t *wsum, ui
     if (lane == kWave - 1)
         wsum[w] = x;
     __syncthreads();
-    uint32_t before = 0, all = 0;
+    if (w == 0) {
+        const uint32_t t = lane < kGenWaves ? wsum[lane] : 0u;
+        uint32_t y = t;
 #pragma unroll
-    for (int k = 0; k < (int)(kGenThreads / kWave); ++k) {
-        const uint32_t s = wsum[k];
-        before += (k < w) ? s : 0u;
-        all += s;
+        for (int s = 1; s < kGenWaves; s <<= 1) {
+            const uint32_t u = __shfl_up(y, s);
+            if (lane >= s)
+                y += u;
+        }
+        if (lane < kGenWaves)
+            wsum[kGenWaves + lane] = y - t;
+        if (lane == kGenWaves - 1)
+            wsum[2 * kGenWaves] = y;
     }
-    *total = all;
-    return before + x - v;
+    __syncthreads();
+    *total = wsum[2 * kGenWaves];
+    return wsum[kGenWaves + w] + x - v;
+}
+
+// Record stage layout in LDS: per partner block J a pair of words at 2J
+// (count, then offset), for J <= NJ, the pair count rounded up to even so
+// that the stage that follows is 16-byte aligned. Block NJ collects the
+// slots that make no record (self pairs, words past m, calls past the
+// range), so every slot takes one unconditional counting step.
+__host__ __device__ __forceinline__ uint32_t gen_pairs(uint32_t NJ)
+{
+    return (NJ + 2u) & ~1u;
 }
 
 // kMod: 0 the binary64 remainder, 1 the binary32 one, 2 the binary32 one
-// with a 24-bit multiply (n < 2^24).
+// with a 24-bit multiply (n < 2^24), 3 the one-sided binary32 one
+// (4096 <= n <= 2^23, inv_lo from gen_inv_lo).
 template <int kMod>
-__global__ __launch_bounds__(kGenThreads) void k_bkt_generate(Inst I, BucketGeom B)
+__global__ __launch_bounds__(kGenThreads) void k_bkt_generate(Inst I, BucketGeom B, float inv_lo)
 {
-    extern __shared__ uint32_t lds_u32[];
-    __shared__ uint32_t wsum[kGenThreads / kWave];
-    // counts and offsets per partner block first, so that their LDS
-    // addresses are small constants plus the block index
-    uint32_t *cnt = lds_u32;               // [NJ]
-    uint32_t *pre = cnt + B.NJ;            // [NJ]
-    uint32_t *stage = pre + B.NJ;          // [kRangeSlots]
+    extern __shared__ __align__(16) uint32_t lds_u32[];
+    __shared__ uint32_t wsum[2 * kGenWaves + 1];
+    const uint32_t NJ = B.NJ;
+    uint32_t *cp = lds_u32;                         // [2 gen_pairs(NJ)]: count, offset
+    uint32_t *stage = lds_u32 + 2 * gen_pairs(NJ);  // [kRangeSlots]
     const uint32_t tid = threadIdx.x;
     const uint64_t r = blockIdx.x;
     const uint64_t call_lo = r * kRangeCalls;
     const uint64_t call_hi = min(call_lo + kRangeCalls, I.calls);
+    const uint32_t ncalls = (uint32_t)(call_hi - call_lo);
     const uint32_t i0 = (uint32_t)(call_lo / I.C);
     const uint32_t c0 = (uint32_t)(call_lo - (uint64_t)i0 * I.C);
-    for (uint32_t k = tid; k < B.NJ; k += kGenThreads)
-        cnt[k] = 0;
+    for (uint32_t k = tid; k < 2 * gen_pairs(NJ); k += kGenThreads)
+        cp[k] = 0;
     if (tid == 0) {
         B.start[2 * r + 0] = i0;  // source and call of the range's first call
         B.start[2 * r + 1] = c0;
@@ -102,80 +123,101 @@ __global__ __launch_bounds__(kGenThreads) void k_bkt_generate(Inst I, BucketGeom
     }
     const uint32_t step_q = kGenThreads / I.C;
     const uint32_t step_r = kGenThreads - step_q * I.C;
+    // The record's bits above its word and partner fields: the call offset
+    // in the range, or for LDS blocks (source offset in the range, call
+    // within the point). Both advance by dH per call, and the second by cH
+    // more when the call within the point wraps to the next source.
+    uint32_t hb, dH, cH;
+    const uint32_t w_shift = B.lds ? B.bshift : 16u;
+    if (B.lds) {
+        const uint32_t s = B.bshift + 2;
+        hb = (((ii - i0) << B.tc_bits) | cc) << s;
+        dH = ((step_q << B.tc_bits) + step_r) << s;
+        cH = ((1u << B.tc_bits) - I.C) << s;
+    } else {
+        hb = tid << kRecOffShift;
+        dH = kGenThreads << kRecOffShift;
+        cH = 0;
+    }
+    // word w of a call is a sample iff 4 cc + w < m; calls past the range
+    // get a call index no word passes
+    uint32_t thr[4];
+#pragma unroll
+    for (int w = 0; w < 4; ++w)
+        thr[w] = I.m > (uint32_t)w ? I.m - (uint32_t)w : 0u;
     const uint32_t pmask = (1u << B.bshift) - 1u;
-    // key: partner block << 16 | rank of the record within its block
+    // key: byte offset of the block's pair << 16 | rank of the record in it
     uint32_t key[4 * kCallsPerThread], rec[4 * kCallsPerThread];
-    uint32_t self = 0;
+    // kAll: every call of the range is live and has four samples (m is a
+    // multiple of 4), so only self pairs make no record
+    auto count = [&]<bool kAll>() {
 #pragma unroll
-    for (uint32_t c = 0; c < kCallsPerThread; ++c) {
-        const uint32_t off = c * kGenThreads + tid;
-        const bool live = call_lo + off < call_hi;
-        const uint32_t nvalid = live ? min(4u, I.m - 4u * cc) : 0u;
-        const Words4 W = philox10(cc, ii, I.key0, I.key1);
-        // the record's fields other than the partner and its word
-        const uint32_t hi_bits = B.lds ? (((ii - i0) << B.tc_bits) | cc) << (B.bshift + 2)
-                                       : (off << kRecOffShift);
-        const uint32_t w_shift = B.lds ? B.bshift : 16u;
+        for (uint32_t c = 0; c < kCallsPerThread; ++c) {
+            const bool live = kAll || tid < ncalls - min(ncalls, c * kGenThreads);
+            const uint32_t cc4 = live ? 4u * cc : 0xFFFFFFF0u;
+            const Words4 W = philox10(cc, ii, I.key0, I.key1);
 #pragma unroll
-        for (int w = 0; w < 4; ++w) {
-            uint32_t kk = ~0u, rr = 0;
-            if ((uint32_t)w < nvalid) {
-                const uint32_t j = kMod == 2   ? mod_f32_n24(W.w[w], I.n, I.inv_nf)
+            for (int w = 0; w < 4; ++w) {
+                const uint32_t j = kMod == 3   ? mod_f32_floor(W.w[w], I.n, inv_lo)
+                                   : kMod == 2 ? mod_f32_n24(W.w[w], I.n, I.inv_nf)
                                    : kMod == 1 ? mod_f32(W.w[w], I.n, I.inv_nf)
                                                : mod_exact(W.w[w], I.n, I.inv_n);
-                if (j == ii) {
-                    ++self;
-                } else {
-                    const uint32_t J = j >> B.bshift;
-                    kk = (J << 16) | atomicAdd(cnt + J, 1u);
-                    rr = hi_bits | ((uint32_t)w << w_shift) | (j & pmask);
-                }
+                const bool none = (j == ii) | (!kAll && cc4 >= thr[w]);
+                const uint32_t J = none ? NJ : (j >> B.bshift);
+                const uint32_t rank = atomicAdd(cp + 2 * J, 1u);
+                key[4 * c + w] = (J << 19) | rank;
+                rec[4 * c + w] = (j & pmask) | hb | ((uint32_t)w << w_shift);
             }
-            key[4 * c + w] = kk;
-            rec[4 * c + w] = rr;
+            cc += step_r;
+            ii += step_q;
+            hb += dH;
+            if (cc >= I.C) {
+                cc -= I.C;
+                ++ii;
+                hb += cH;
+            }
         }
-        cc += step_r;
-        ii += step_q;
-        if (cc >= I.C) {
-            cc -= I.C;
-            ++ii;
-        }
-    }
+    };
+    if (ncalls == kRangeCalls && (I.m & 3u) == 0)
+        count.template operator()<true>();
+    else
+        count.template operator()<false>();
     __syncthreads();
-    const uint32_t v = tid < B.NJ ? cnt[tid] : 0u;
+    const uint32_t v = tid < NJ ? cp[2 * tid] : 0u;
     uint32_t total;
     const uint32_t ex = gen_exclusive(v, wsum, &total);
-    if (tid < B.NJ) {
-        pre[tid] = ex;
-        B.seg[(r * B.NJ + tid) * 2 + 0] = ex;
-        B.seg[(r * B.NJ + tid) * 2 + 1] = v;
+    if (tid < NJ) {
+        cp[2 * tid + 1] = ex;
+        *reinterpret_cast<uint2 *>(B.seg + (r * NJ + tid) * 2) = make_uint2(ex, v);
+    }
+    if (tid == 0) {
+        // the slots without a record go past the records
+        cp[2 * NJ + 1] = total;
+        // self pairs: the range's sample slots (words below m of its calls;
+        // the last call of a point has m - 4 (C - 1) of them) less its records
+        const uint32_t wraps = (c0 + ncalls) / I.C;  // points whose last call is in the range
+        const uint64_t slots = 4ull * ncalls - (uint64_t)(4u * I.C - I.m) * wraps;
+        const uint64_t self = slots - total;
+        if (self)
+            atomicAdd(B.hdr + 1, (unsigned long long)self);
     }
     __syncthreads();
+    const char *cpb = reinterpret_cast<const char *>(cp);
 #pragma unroll
     for (uint32_t k = 0; k < 4 * kCallsPerThread; ++k) {
-        if (key[k] != ~0u)
-            stage[pre[key[k] >> 16] + (key[k] & 0xFFFFu)] = rec[k];
+        const uint32_t base = *reinterpret_cast<const uint32_t *>(cpb + (key[k] >> 16) + 4);
+        stage[base + (key[k] & 0xFFFFu)] = rec[k];
     }
     __syncthreads();
     uint32_t *dst = B.rec + r * B.region;
-    // stage starts 2*NJ words into LDS: copy out in 16-byte pieces when that
-    // keeps both sides aligned, else word by word
-    if ((B.NJ & 1u) == 0) {
-        for (uint32_t k = 4 * tid; k < total; k += 4 * kGenThreads) {
-            if (k + 4 <= total) {
-                *reinterpret_cast<uint4 *>(dst + k) = *reinterpret_cast<const uint4 *>(stage + k);
-            } else {
-                for (uint32_t e = k; e < total; ++e)
-                    dst[e] = stage[e];
-            }
+    for (uint32_t k = 4 * tid; k < total; k += 4 * kGenThreads) {
+        if (k + 4 <= total) {
+            *reinterpret_cast<uint4 *>(dst + k) = *reinterpret_cast<const uint4 *>(stage + k);
+        } else {
+            for (uint32_t e = k; e < total; ++e)
+                dst[e] = stage[e];
         }
-    } else {
-        for (uint32_t k = tid; k < total; k += kGenThreads)
-            dst[k] = stage[k];
     }
-    const int slots[1] = {1};
-    const uint32_t sv[1] = {self};
-    block_count_add<1>(B.hdr, slots, sv);
 }
 
 // Before generate: no valid sample, no self pairs counted yet.
@@ -292,21 +334,36 @@ uint64_t sample_tag(int64_t n, int64_t m, uint64_t seed, uint32_t bshift, uint32
     return h | 1ull;
 }
 
+// The one-sided remainder's inverse: (1/n)(1 - 2^-21) rounded down to
+// binary32, or 0 where that remainder does not apply (n outside
+// [4096, 2^23]).
+static float gen_inv_lo(uint32_t n)
+{
+    if (n < 4096u || n > (1u << 23))
+        return 0.0f;
+    const double x = (1.0 / (double)n) * (1.0 - 0x1p-21);
+    float v = (float)x;
+    if ((double)v > x)
+        v = nextafterf(v, 0.0f);
+    return v;
+}
+
 hipError_t launch_bucket_generate(const Inst &I, const BucketGeom &B, hipStream_t st)
 {
     if (B.ranges > 0x7FFFFFFFull || B.NJ > kMaxPartnerBlocks)
         return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_bkt_prepare, dim3(1), dim3(64), 0, st, B, 1);
-    const size_t lds = ((size_t)kRangeSlots + 2 * (size_t)B.NJ) * sizeof(uint32_t);
-    if (I.inv_nf != 0.0f && I.n < (1u << 24))
-        hipLaunchKernelGGL(k_bkt_generate<2>, dim3((unsigned)B.ranges), dim3(kGenThreads), lds,
-                           st, I, B);
+    const size_t lds = ((size_t)kRangeSlots + 2 * (size_t)gen_pairs(B.NJ)) * sizeof(uint32_t);
+    const float inv_lo = gen_inv_lo(I.n);
+    const dim3 grid((unsigned)B.ranges), block(kGenThreads);
+    if (inv_lo != 0.0f)
+        hipLaunchKernelGGL(k_bkt_generate<3>, grid, block, lds, st, I, B, inv_lo);
+    else if (I.inv_nf != 0.0f && I.n < (1u << 24))
+        hipLaunchKernelGGL(k_bkt_generate<2>, grid, block, lds, st, I, B, 0.0f);
     else if (I.inv_nf != 0.0f)
-        hipLaunchKernelGGL(k_bkt_generate<1>, dim3((unsigned)B.ranges), dim3(kGenThreads), lds,
-                           st, I, B);
+        hipLaunchKernelGGL(k_bkt_generate<1>, grid, block, lds, st, I, B, 0.0f);
     else
-        hipLaunchKernelGGL(k_bkt_generate<0>, dim3((unsigned)B.ranges), dim3(kGenThreads), lds,
-                           st, I, B);
+        hipLaunchKernelGGL(k_bkt_generate<0>, grid, block, lds, st, I, B, 0.0f);
     hipLaunchKernelGGL(k_bkt_seal, dim3(1), dim3(64), 0, st, B);
     return hipGetLastError();
 }

@@ -186,6 +186,22 @@ __device__ __forceinline__ uint32_t mod_f32_n24(uint32_t w, uint32_t n, float in
     return min(min(r, r + n), r - n);
 }
 
+// w mod n for 4096 <= n <= 2^23 from a quotient estimate that never exceeds
+// w/n. inv is (1/n)(1 - 2^-21) rounded down to binary32, so it lies within
+// 2^-23 (relative) below that value; fl32(w) and the rounded product add a
+// relative error below 2^-24 each. The estimate p then satisfies
+// (w/n)(1 - 3 * 2^-22) < p < w/n, and as w/n < 2^32 / 2^12 = 2^20 it is
+// less than 0.75 below w/n: its truncation q is floor(w/n) or one less.
+// So r = w - q n lies in [0, 2n), and min(r, r - n) is the remainder (r - n
+// wraps above r when r < n). q < 2^20 and -n >= -2^23 are signed 24-bit
+// operands, so q n and the subtraction are one 24-bit multiply-add.
+__device__ __forceinline__ uint32_t mod_f32_floor(uint32_t w, uint32_t n, float inv)
+{
+    const int32_t q = (int32_t)(uint32_t)((float)w * inv);
+    const uint32_t r = (uint32_t)((int32_t)w + __mul24(q, -(int32_t)n));
+    return min(r, r - n);
+}
+
 // The four partners of one Philox call: its words mod n. The branch is
 // uniform (one instance per wavefront), so only one side runs.
 __device__ __forceinline__ void partners4(const Inst &I, const Words4 &W, uint32_t j[4])

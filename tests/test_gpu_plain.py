@@ -221,6 +221,30 @@ def test_partner_draws_at_the_remainder_limit(sng, orc, n):
     assert np.array_equal(got, ref)
 
 
+@pytest.mark.parametrize("m", [4, 7], ids=["m4", "m7"])
+def test_partner_blocks_at_the_remainder_switches(sng, orc, m):
+    """The partner-block sampler draws partners with a one-sided binary32
+    remainder for 4096 <= n <= 2^23 and with the two-sided one around it;
+    m = 7 leaves three words of each point's last call unused, and the
+    sizes leave the last generator range partial. With every point equal
+    every slot is accepted, so the degrees check every drawn partner index
+    and every source against the oracle's."""
+    import torch
+    eps, seed = 1.0, 0xB0C5
+    for n in [4095, 4096, 4097, 40_961, (1 << 23) - 1, 1 << 23, (1 << 23) + 1]:
+        print("remainder switch n", n, "m", m, flush=True)
+        X = torch.zeros((n, 2), dtype=torch.float32, device="cuda:0")
+        deg, ws = sng.degrees(X, m, eps, seed, cfg=sng.Config(schedule=2))
+        st = sng.stats(ws)
+        got = deg.cpu().numpy().view(np.uint32)
+        del deg, ws, X
+        ref, slots, self_pairs, accepted = orc.degrees(np.zeros((n, 2), np.float32), m, eps,
+                                                       seed)
+        assert st.slots == slots == n * m
+        assert st.self_pairs == self_pairs and st.accepted == accepted, n
+        assert np.array_equal(got, ref), n
+
+
 @pytest.mark.timeout(600)
 @pytest.mark.parametrize("sigma", [1.0, 0.25])
 def test_mixture16d_full_size(sng, orc, sigma):
