@@ -472,8 +472,10 @@ __device__ __forceinline__ void eval_ticket_lds(const Inst &I, const BucketGeom 
             return Row::fetch(X + (int64_t)r * ld, 0, D);
     };
 
-    // the window table of windows [wb, wb + 64): lane w holds window wb + w
-    uint32_t t_rec = 0, t_src = 0, t_n = 0;
+    // the window table of windows [wb, wb + 64): lane w holds window wb + w,
+    // its record base and (first source << 7 | record count); sources are
+    // below n <= kMaxPartnerBlocks * 2^15 = 2^25 in this form
+    uint32_t t_rec = 0, t_sn = 0;
     auto build = [&](uint32_t wb) {
         const uint32_t w = wb + (uint32_t)lane;
         // its segment: the first l with winc_l > w (winc is non-decreasing)
@@ -490,8 +492,8 @@ __device__ __forceinline__ void eval_ticket_lds(const Inst &I, const BucketGeom 
                            (uint32_t)kWave;
         const uint32_t c = (uint32_t)__builtin_amdgcn_ds_bpermute((int)a, (int)cnt_l);
         t_rec = (uint32_t)__builtin_amdgcn_ds_bpermute((int)a, (int)base_l) + o;
-        t_src = (uint32_t)__builtin_amdgcn_ds_bpermute((int)a, (int)i0_l);
-        t_n = (w < total && c > o) ? min(c - o, (uint32_t)kWave) : 0u;
+        const uint32_t src = (uint32_t)__builtin_amdgcn_ds_bpermute((int)a, (int)i0_l);
+        t_sn = (src << 7) | ((w < total && c > o) ? min(c - o, (uint32_t)kWave) : 0u);
     };
     // window k's entries (k in the current table)
     uint32_t wb = 0;
@@ -502,48 +504,48 @@ __device__ __forceinline__ void eval_ticket_lds(const Inst &I, const BucketGeom 
         for (int k = 0; k < P; ++k) {
             const int at = (int)(k0 + (uint32_t)k - wb);  // < 64 (tables are rebuilt first)
             w_rec[k] = (uint32_t)__builtin_amdgcn_readlane((int)t_rec, at);
-            w_src[k] = (uint32_t)__builtin_amdgcn_readlane((int)t_src, at);
-            w_n[k] = (uint32_t)__builtin_amdgcn_readlane((int)t_n, at);
+            const uint32_t sn = (uint32_t)__builtin_amdgcn_readlane((int)t_sn, at);
+            w_src[k] = sn >> 7;
+            w_n[k] = sn & 127u;
         }
     };
     // kLaneRows: lane t holds element t mod D of source row src + t / D
     // (rows src .. src + 64/D - 1 cover every source of a range)
     const uint32_t lr_row = (uint32_t)lane / (uint32_t)D;
     const uint32_t lr_el = (uint32_t)lane - lr_row * (uint32_t)D;
-    uint32_t nv[P];
-    float nrow[P];
-    auto issue = [&]() {  // loads of the windows in w_* (harmless ones for empty windows)
+    // The loads of P windows: records, and with kLaneRows the source rows.
+    struct Win {
+        uint32_t v[P], src[P], n[P];
+        float row[P];
+    };
+    // Lanes past a window's records, and (kLaneRows) past the rows a range
+    // can touch, load nothing: their buffer offset is out of range, which
+    // reads zero without a memory request.
+    constexpr uint32_t kNoLoad = 0xFFFFFFF0u;
+    const uint32_t lr_lanes = ((I.C - 1u + (uint32_t)kRangeCalls - 1u) / I.C + 1u) * (uint32_t)D;
+    auto issue = [&](Win &S) {  // windows in w_* (harmless loads for empty ones)
 #pragma unroll
         for (int k = 0; k < P; ++k) {
             if constexpr (kLaneRows) {
                 const uint32_t r = w_src[k] + lr_row;
                 if constexpr (kBuf) {
                     // rows past the last one read as zero through the buffer
-                    nrow[k] = bld1(rs, __umul24(lr_row, ld4) + w_src[k] * ld4 + lr_el * 4u);
+                    S.row[k] = bld1(rs, (uint32_t)lane < lr_lanes
+                                            ? __umul24(lr_row, ld4) + w_src[k] * ld4 + lr_el * 4u
+                                            : kNoLoad);
                 } else {
-                    nrow[k] = X[(int64_t)(r < I.n ? r : I.n - 1u) * ld + lr_el];
+                    S.row[k] = X[(int64_t)(r < I.n ? r : I.n - 1u) * ld + lr_el];
                 }
             }
-            nv[k] = __builtin_amdgcn_raw_buffer_load_b32(rrec, (int)((w_rec[k] + lane) * 4u), 0,
-                                                        0);
+            S.v[k] = __builtin_amdgcn_raw_buffer_load_b32(
+                rrec, (int)((uint32_t)lane < w_n[k] ? (w_rec[k] + lane) * 4u : kNoLoad), 0, 0);
+            S.src[k] = w_src[k];
+            S.n[k] = w_n[k];
         }
     };
-    static_assert(kWave % P == 0, "windows per iteration divide the table");
-    take(0);
-    issue();
-    for (uint32_t k0 = 0; k0 < total; k0 += P) {  // wave-uniform
-        uint32_t v[P], c_src[P], c_n[P];
-        float crow[P];
-#pragma unroll
-        for (int k = 0; k < P; ++k) {
-            v[k] = nv[k];
-            crow[k] = nrow[k];
-            c_src[k] = w_src[k];
-            c_n[k] = w_n[k];
-        }
-        // the next P windows (a new table every 64 windows; windows past the
-        // last have no records and load harmlessly)
-        const uint32_t k1 = k0 + P;
+    // windows k1 .. k1 + P - 1 into w_* (a new table every 64 windows;
+    // windows past the last have no records)
+    auto next = [&](uint32_t k1) {
         if (k1 - wb >= (uint32_t)kWave && k1 < total) {
             wb = k1;
             build(wb);
@@ -554,59 +556,82 @@ __device__ __forceinline__ void eval_ticket_lds(const Inst &I, const BucketGeom 
             for (int k = 0; k < P; ++k)
                 w_n[k] = 0;
         }
-        issue();  // the next P windows load while these are decided
-
-        uint32_t ii[P], cj[P];
-        bool live[P];
-        Buf bi[P], bj[P];
-        bool bad = false;
+    };
+    static_assert(kWave % P == 0, "windows per iteration divide the table");
+    // kDepth sets of windows load ahead: windows k0 + P .. k0 + kDepth*P are
+    // in flight while windows k0 are decided (two sets where the registers
+    // allow). A step takes the windows of its set (already loaded), reloads
+    // the set with the windows kDepth steps on, then decides.
+    constexpr int kDepth = D <= 5 ? 2 : 1;
+    auto step = [&](Win &S, uint32_t k0) {
+        uint32_t v[P], c_src[P], c_n[P];
+        float crow[P];
 #pragma unroll
         for (int k = 0; k < P; ++k) {
-            live[k] = (uint32_t)lane < c_n[k];
+            v[k] = S.v[k];
+            crow[k] = S.row[k];
+            c_src[k] = S.src[k];
+            c_n[k] = S.n[k];
+        }
+        next(k0 + kDepth * P);
+        issue(S);
+
+        uint32_t ii[P], cj[P];
+        Buf bi[P], bj[P];
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
             const uint32_t so = v[k] >> si_shift;
             ii[k] = c_src[k] + so;
             const uint32_t off = v[k] & pmask;
             cj[k] = jbase + off;
-            bad |= live[k] & ((ii[k] >= I.n) | (cj[k] >= I.n) |
-                              (kLaneRows & (so >= (uint32_t)(kWave / D))));
             if constexpr (kLaneRows) {
-                // the permutes read lanes so*D + e mod 64; a bad so is caught above
+                // the permutes read lanes so*D + e mod 64 (any lane: a bad so
+                // is caught before a decision)
                 const uint32_t a = __umul24(so, 4u * (uint32_t)D);
 #pragma unroll
                 for (int e = 0; e < D; ++e)
                     bi[k].v[e] = __int_as_float(
                         __builtin_amdgcn_ds_bpermute((int)(a + 4u * e), __float_as_int(crow[k])));
             } else {
-                bi[k] = row_at(live[k] ? ii[k] : 0u);  // row 0 always exists
+                // rows past X read as zero through the buffer; the plain
+                // form clamps the index (a bad one is caught before a decision)
+                bi[k] = row_at(kBuf ? ii[k] : min(ii[k], I.n - 1u));
             }
             // off < 2^bshift rows: inside the block's LDS whether staged or not
             bj[k] = Row::fetch_lds(lblk + __umul24(off, (uint32_t)D));
         }
-        if (__ballot(bad) != 0) {  // never for a valid sample
-            if (bad)
-                atomicAdd(I.cnt + kCntOverflow, 1ull);
-#pragma unroll
-            for (int k = 0; k < P; ++k)
-                live[k] = live[k] & ((ii[k] < I.n) & (cj[k] < I.n) &
-                                     (!kLaneRows | ((v[k] >> si_shift) < (uint32_t)(kWave / D))));
-        }
         float F[P], Q[P];
-        bool act = false;
+        uint64_t act = 0;
 #pragma unroll
         for (int k = 0; k < P; ++k) {
+            const bool live = (uint32_t)lane < c_n[k];
             if constexpr (Pol::kDot) {
                 const float2 pq = Row::partial2_dot(bi[k], bj[k], 0, D);
                 F[k] = pq.x;
                 Q[k] = pq.y;
-                act |= live[k] && pol.may_act_dot(F[k], Q[k]);
+                act |= __ballot(live && pol.may_act_dot(F[k], Q[k]));
             } else {
                 F[k] = Row::partial2(bi[k], bj[k], 0, D);
                 Q[k] = 0.0f;
-                act |= live[k] && pol.may_act(F[k]);
+                act |= __ballot(live && pol.may_act(F[k]));
             }
         }
-        if (__ballot(act) == 0)
-            continue;  // wave-uniform: every live slot here is surely rejected
+        if (act == 0)
+            return;  // wave-uniform: every live slot here is surely rejected
+        // Records outside the instance (never for a valid sample) are counted
+        // and their windows dropped before anything is written.
+        bool live[P], bad = false;
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            live[k] = (uint32_t)lane < c_n[k];
+            bad |= live[k] & ((ii[k] >= I.n) | (cj[k] >= I.n) |
+                              (kLaneRows & ((v[k] >> si_shift) >= (uint32_t)(kWave / D))));
+        }
+        if (__ballot(bad) != 0) {
+            if (bad)
+                atomicAdd(I.cnt + kCntOverflow, 1ull);
+            return;
+        }
 #pragma unroll
         for (int k = 0; k < P; ++k) {
             if (!live[k])
@@ -623,6 +648,21 @@ __device__ __forceinline__ void eval_ticket_lds(const Inst &I, const BucketGeom 
                                   ((vk >> (B.bshift + 2)) & ((1u << B.tc_bits) - 1u));
                        },
                        (int)((vk >> B.bshift) & 3u), 0, tally);
+        }
+    };
+    Win A, Bw;
+    take(0);
+    issue(A);
+    if constexpr (kDepth == 2) {
+        next(P);
+        issue(Bw);
+    }
+    for (uint32_t k0 = 0; k0 < total; k0 += kDepth * P) {  // wave-uniform
+        step(A, k0);
+        if constexpr (kDepth == 2) {
+            if (k0 + P >= total)
+                break;
+            step(Bw, k0 + P);
         }
     }
 }

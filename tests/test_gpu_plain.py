@@ -221,6 +221,24 @@ def test_partner_draws_at_the_remainder_limit(sng, orc, n):
     assert np.array_equal(got, ref)
 
 
+@pytest.mark.parametrize("d", range(1, 9))
+def test_lds_blocks_every_small_d(sng, orc, d):
+    """Rows of at most eight floats: the partner-block schedule stages whole
+    blocks in LDS, with one evaluate kernel per d. With about 140 samples per
+    point every lane loads its own source row; with about 2200 a window's
+    source rows come from one coalesced load shared through cross-lane
+    permutes (for d <= 4). The sizes are ragged and span several blocks."""
+    rng = np.random.default_rng(300 + d)
+    for n, s in [(70_001, 0.002), (20_003, 0.11)]:
+        X = wl.random_instance(rng, n, d, "blobs", spread=0.01)
+        eps = 0.012 * np.sqrt(d)
+        print("lds d", d, "n", n, "s", s, flush=True)
+        ref = orc.dbscan(X, eps, 4, 99, s=s)
+        gl, gd, st = run(sng, X, s, eps, 4, 99, cfg=sng.Config(schedule=2))
+        assert_same(gl, gd, ref, "d=%d n=%d" % (d, n))
+        assert st.accepted == ref.accepted and st.self_pairs == ref.self_pairs
+
+
 @pytest.mark.parametrize("m", [4, 7], ids=["m4", "m7"])
 def test_partner_blocks_at_the_remainder_switches(sng, orc, m):
     """The partner-block sampler draws partners with a one-sided binary32
