@@ -401,7 +401,7 @@ __global__ __launch_bounds__(256) void k_bkt_eval_sweep(Inst I, BucketGeom B, Sw
 constexpr uint32_t kLdsThreads = 1024;
 constexpr uint32_t kLdsWaves = kLdsThreads / kWave;
 constexpr uint32_t kLdsTicketRanges = 64;
-constexpr uint64_t kLdsChunkRanges = 16384;
+constexpr uint64_t kLdsChunkRanges = 32768;
 constexpr int kLdsWindows = 4;  // windows decided per iteration of a wavefront
 static_assert(kLdsTicketRanges <= kWave, "one lane per segment of a ticket");
 
