@@ -75,7 +75,8 @@ typedef enum {
     SNG_EWORKSPACE = -3, /* workspace missing or smaller than required */
     SNG_EHIP = -4,       /* a HIP runtime call or kernel launch failed */
     SNG_EOVERFLOW = -5,  /* reported by sng_stats_read: a device queue overflowed */
-    SNG_ENOTIMPL = -6    /* requested form not available for these arguments */
+    SNG_ENOTIMPL = -6,   /* requested form not available for these arguments */
+    SNG_EIO = -7         /* a file could not be opened, read or written */
 } sng_status;
 
 typedef enum {
@@ -95,6 +96,9 @@ typedef struct {
     int32_t reuse_sample;    /* 1: evaluate the sample sng_sample left in the workspace */
     int32_t out_degree;      /* 1: degree = a point's own accepted samples (see below) */
     int32_t simple_graph;    /* 1: degree = distinct accepted neighbours (see below) */
+    int32_t mfma_waves;      /* mixed form: wavefronts per block of the MFMA pass: 1, 2, 4 */
+    int32_t mfma_ksteps;     /* mixed form: 32-wide K-steps loaded together: 4, 8, 16 */
+    int32_t hook_blocks;     /* post-processing: blocks of the hook launch, 256..65536 */
 } sng_config;
 /* schedule: the partner-block form sorts the sample slots by partner block
  * before gathering, so that a block's rows are read from LDS (rows of d <= 8
@@ -225,6 +229,53 @@ int sng_autotune_lookup(const float *X, int64_t n, int32_t d, int64_t ld, int64_
                         sng_config *out);
 /* Empties the autotune cache. Host call. */
 int sng_autotune_clear(void);
+
+/* The other tuned launch shapes, each timed like sng_autotune (`trials` timed
+ * calls per candidate after one warm-up, HIP events on `stream`, which is
+ * synchronised; *best, *best_ms, *tried as there) and stored in the same
+ * cache under a key that also names the form, so a tuned shape is only used
+ * by calls of its own form and precision:
+ *   sng_autotune_lowp: sng_dbscan_lowp's arguments; candidates mfma_waves x
+ *     mfma_ksteps (the wavefronts per block of the MFMA pass, and how many
+ *     32-wide K-steps of partner fragments it loads together). Key (prec, d,
+ *     16-byte row alignment, ceil(log2 n), ceil(log2 m)); sng_dbscan_lowp
+ *     calls without launch fields of their own then use it.
+ *   sng_autotune_hook: sng_cluster's arguments (a sng_degrees call must have
+ *     left its accept bits in the workspace); candidates hook_blocks, the
+ *     grid of the hook launch. Stored into the plain form's entry of the
+ *     shape class (created with default pass fields if there is none), used
+ *     by sng_dbscan and sng_cluster.
+ *   sng_autotune_batch: sng_dbscan_batch's arguments; candidates lanes per
+ *     pair x rows in flight x chunks per wave of the batched pass. Key (d,
+ *     row alignment of every instance, ceil(log2 max n), ceil(log2 max m));
+ *     sng_dbscan_batch and sng_batch_plan_create then use it.
+ * Every candidate computes the same results; labels and degrees hold the
+ * last candidate's. */
+int sng_autotune_lowp(const float *X, int64_t n, int32_t d, int64_t ld, const uint16_t *X_lp,
+                      int64_t ld_lp, float lp_scale, int32_t prec, double s, double eps,
+                      int32_t min_pts, uint64_t seed, int32_t *labels, uint32_t *degrees,
+                      void *workspace, size_t ws_bytes, int32_t trials, sng_config *best,
+                      float *best_ms, int32_t *tried, void *stream);
+int sng_autotune_hook(const float *X, int64_t n, int32_t d, int64_t ld, int64_t m, double eps,
+                      uint64_t seed, int32_t min_pts, const uint32_t *degrees, int32_t *labels,
+                      void *workspace, size_t ws_bytes, int32_t trials, sng_config *best,
+                      float *best_ms, int32_t *tried, void *stream);
+int sng_autotune_batch(int32_t count, const float *const *X, const int64_t *n, int32_t d,
+                       const int64_t *ld, const double *s, const double *eps,
+                       const int32_t *min_pts, const uint64_t *seed, int32_t *const *labels,
+                       uint32_t *const *degrees, void *workspace, size_t ws_bytes, int32_t trials,
+                       sng_config *best, float *best_ms, int32_t *tried, void *stream);
+
+/* The autotune cache on disk: sng_autotune_save writes every entry to the
+ * text file `path` (replacing it; a header line, then one line per entry:
+ * form (0 plain, 1 bfloat16, 2 float16, 3 batch), d, row alignment flag,
+ * ceil(log2 n), ceil(log2 m) and the eleven sng_config fields);
+ * sng_autotune_load merges such a file into the cache (its entries replace
+ * equal keys). A file that does not parse, or holds an invalid
+ * configuration, changes nothing and returns SNG_EINVAL; a file that cannot
+ * be opened or written returns SNG_EIO. Host calls. */
+int sng_autotune_save(const char *path);
+int sng_autotune_load(const char *path);
 
 /* Post-processing (Algorithm 1: core points, components of the core
  * subgraph, border assignment) continuing from the accept bits that the last

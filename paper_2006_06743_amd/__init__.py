@@ -9,6 +9,7 @@ the current stream. The C ABI is documented in include/sng.h.
 from __future__ import annotations
 
 import ctypes
+import os
 from dataclasses import dataclass
 from typing import Optional, Sequence
 
@@ -20,7 +21,8 @@ from ._lib import (SNG_BF16, SNG_FP16, SNG_FP32, SNG_SIM_COSINE, SNG_SIM_DOT, SN
 
 __all__ = ["dbscan", "dbscan_noalloc", "dbscan_lowp", "dbscan_similarity", "degrees", "sample", "cluster",
            "compact_labels", "similarity_workspace_size", "SNG_SIM_DOT", "SNG_SIM_COSINE",
-           "autotune", "autotune_lookup", "autotune_clear",
+           "autotune", "autotune_lookup", "autotune_clear", "autotune_save", "autotune_load",
+           "autotune_hook", "autotune_lowp", "autotune_batch",
            "graph_labels", "sweep", "batch", "BatchPlan",
            "samples_per_point", "Config", "Stats", "SNGError", "SNG_FP32", "SNG_BF16",
            "SNG_FP16", "load"]
@@ -41,11 +43,15 @@ class Config:
     reuse_sample: int = 0  # 1: evaluate the sample that sample() left in the workspace
     out_degree: int = 0    # 1: a point's degree counts only its own accepted samples
     simple_graph: int = 0  # 1: a point's degree counts its distinct accepted neighbours
+    mfma_waves: int = 0    # mixed form: wavefronts per block of the MFMA pass (1, 2, 4)
+    mfma_ksteps: int = 0   # mixed form: 32-wide K-steps loaded together (4, 8, 16)
+    hook_blocks: int = 0   # post-processing: grid of the hook launch (256..65536)
 
     def c(self):
         return ctypes.byref(sng_config(self.lanes_per_pair, self.chunks_per_wave,
                                        self.stage_lds, self.prefetch, self.schedule,
-                                       self.reuse_sample, self.out_degree, self.simple_graph))
+                                       self.reuse_sample, self.out_degree, self.simple_graph,
+                                       self.mfma_waves, self.mfma_ksteps, self.hook_blocks))
 
 
 @dataclass
@@ -152,7 +158,8 @@ def sample(n: int, d: int, m: int, seed: int, ws: torch.Tensor):
 
 def _config_of(c) -> Config:
     return Config(c.lanes_per_pair, c.chunks_per_wave, c.stage_lds, c.prefetch, c.schedule,
-                  c.reuse_sample, c.out_degree, c.simple_graph)
+                  c.reuse_sample, c.out_degree, c.simple_graph, c.mfma_waves, c.mfma_ksteps,
+                  c.hook_blocks)
 
 
 def autotune(X: torch.Tensor, m: int, eps: float, seed: int, trials: int = 2,
@@ -187,6 +194,36 @@ def autotune_lookup(X: torch.Tensor, m: int) -> Optional[Config]:
 
 def autotune_clear():
     check(_lib.load().sng_autotune_clear(), "sng_autotune_clear")
+
+
+def autotune_save(path: str):
+    """Writes the autotune cache to a text file."""
+    check(_lib.load().sng_autotune_save(os.fsencode(path)), "sng_autotune_save")
+
+
+def autotune_load(path: str):
+    """Merges a file written by autotune_save into the autotune cache."""
+    check(_lib.load().sng_autotune_load(os.fsencode(path)), "sng_autotune_load")
+
+
+def autotune_hook(X: torch.Tensor, m: int, eps: float, seed: int, min_pts: int,
+                  deg: torch.Tensor, ws: torch.Tensor, trials: int = 2,
+                  labels: Optional[torch.Tensor] = None):
+    """Times the hook launch's grid on the post-processing that a prior
+    degrees() call on ws prepared, caches the fastest for the plain form's
+    shape class. Returns (Config, mean ms, candidates timed, labels)."""
+    n, d, ld = _rows(X)
+    if labels is None:
+        labels = torch.empty(n, dtype=torch.int32, device=X.device)
+    best = sng_config()
+    ms = ctypes.c_float()
+    tried = ctypes.c_int32()
+    check(_lib.load().sng_autotune_hook(X.data_ptr(), n, d, ld, int(m), float(eps), int(seed),
+                                        int(min_pts), deg.data_ptr(), labels.data_ptr(),
+                                        ws.data_ptr(), ws.numel(), int(trials),
+                                        ctypes.byref(best), ctypes.byref(ms),
+                                        ctypes.byref(tried), _stream(X)), "sng_autotune_hook")
+    return _config_of(best), ms.value, tried.value, labels
 
 
 def cluster(X: torch.Tensor, m: int, eps: float, seed: int, min_pts: int, deg: torch.Tensor,
@@ -291,6 +328,31 @@ def dbscan_lowp(X: torch.Tensor, X_lp: torch.Tensor, s: float, eps: float, min_p
                                       labels.data_ptr(), deg.data_ptr(), ws.data_ptr(),
                                       ws.numel(), _cfg(cfg), _stream(X)), "sng_dbscan_lowp")
     return labels, deg, ws
+
+
+def autotune_lowp(X: torch.Tensor, X_lp: torch.Tensor, s: float, eps: float, min_pts: int,
+                  seed: int, prec: int = SNG_BF16, lp_scale: float = 1.0, trials: int = 2,
+                  ws: Optional[torch.Tensor] = None):
+    """Times the mixed form's MFMA pass shapes (whole dbscan_lowp calls) and
+    caches the fastest for its precision and shape class. Returns (Config,
+    mean ms, candidates timed, labels, degrees)."""
+    n, d, ld = _rows(X)
+    m = samples_per_point(s, n)
+    labels = torch.empty(n, dtype=torch.int32, device=X.device)
+    deg = torch.empty(n, dtype=torch.int32, device=X.device)
+    if ws is None:
+        ws = _ws(workspace_size(n, d, m, prec), X.device)
+    best = sng_config()
+    ms = ctypes.c_float()
+    tried = ctypes.c_int32()
+    check(_lib.load().sng_autotune_lowp(X.data_ptr(), n, d, ld, X_lp.data_ptr(),
+                                        X_lp.stride(0) if n > 0 else d, float(lp_scale),
+                                        int(prec), float(s), float(eps), int(min_pts), int(seed),
+                                        labels.data_ptr(), deg.data_ptr(), ws.data_ptr(),
+                                        ws.numel(), int(trials), ctypes.byref(best),
+                                        ctypes.byref(ms), ctypes.byref(tried), _stream(X)),
+          "sng_autotune_lowp")
+    return _config_of(best), ms.value, tried.value, labels, deg
 
 
 def graph_labels(n: int, edges: torch.Tensor, min_pts: int, device=None):
@@ -399,6 +461,33 @@ def batch(Xs, s, eps, min_pts, seeds, ws: Optional[torch.Tensor] = None):
                                        ws.data_ptr(), ws.numel(), _stream(Xs[0])),
           "sng_dbscan_batch")
     return labels, degs, ws
+
+
+def autotune_batch(Xs, s, eps, min_pts, seeds, trials: int = 2,
+                   ws: Optional[torch.Tensor] = None):
+    """Times launch shapes of the batched pass on this batch and caches the
+    fastest for its shape class. Returns (Config, mean ms, candidates timed,
+    labels, degrees)."""
+    for x in Xs:
+        _rows(x)
+    dev = Xs[0].device
+    labels = [torch.empty(x.shape[0], dtype=torch.int32, device=dev) for x in Xs]
+    degs = [torch.empty(x.shape[0], dtype=torch.int32, device=dev) for x in Xs]
+    count, d, a = _batch_args(Xs, s, eps, min_pts, seeds, labels, degs)
+    if ws is None:
+        ws = _ws(batch_workspace_size(a[1], d, a[3]), dev)
+    xp, ns, lds, ss, es, ms_, sd, lp, dp = a
+    best = sng_config()
+    ms = ctypes.c_float()
+    tried = ctypes.c_int32()
+    check(_lib.load().sng_autotune_batch(count, xp.ctypes.data, ns.ctypes.data, d,
+                                         lds.ctypes.data, ss.ctypes.data, es.ctypes.data,
+                                         ms_.ctypes.data, sd.ctypes.data, lp.ctypes.data,
+                                         dp.ctypes.data, ws.data_ptr(), ws.numel(), int(trials),
+                                         ctypes.byref(best), ctypes.byref(ms),
+                                         ctypes.byref(tried), _stream(Xs[0])),
+          "sng_autotune_batch")
+    return _config_of(best), ms.value, tried.value, labels, degs
 
 
 class BatchPlan:

@@ -11,8 +11,8 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsng.so")
 
-SNG_OK, SNG_EINVAL, SNG_ERANGE, SNG_EWORKSPACE, SNG_EHIP, SNG_EOVERFLOW, SNG_ENOTIMPL = \
-    0, -1, -2, -3, -4, -5, -6
+SNG_OK, SNG_EINVAL, SNG_ERANGE, SNG_EWORKSPACE, SNG_EHIP, SNG_EOVERFLOW, SNG_ENOTIMPL, SNG_EIO = \
+    0, -1, -2, -3, -4, -5, -6, -7
 SNG_FP32, SNG_BF16, SNG_FP16 = 0, 1, 2
 SNG_SIM_DOT, SNG_SIM_COSINE = 1, 2
 SNG_WS_DIRECT, SNG_WS_SIMPLE_GRAPH = 0x100, 0x200
@@ -22,7 +22,8 @@ EXPORTS = [
     "sng_status_string", "sng_samples_per_point", "sng_workspace_size", "sng_degrees",
     "sng_cluster", "sng_dbscan", "sng_dbscan_lowp", "sng_graph_workspace_size", "sng_graph_labels",
     "sng_compact_labels", "sng_sample", "sng_autotune", "sng_autotune_lookup",
-    "sng_autotune_clear",
+    "sng_autotune_clear", "sng_autotune_lowp", "sng_autotune_hook", "sng_autotune_batch",
+    "sng_autotune_save", "sng_autotune_load",
     "sng_sweep_workspace_size", "sng_dbscan_sweep", "sng_batch_workspace_size",
     "sng_dbscan_batch", "sng_batch_plan_create", "sng_batch_plan_launch",
     "sng_batch_plan_destroy", "sng_stats_read",
@@ -34,7 +35,9 @@ class sng_config(ctypes.Structure):
     _fields_ = [("lanes_per_pair", ctypes.c_int32), ("chunks_per_wave", ctypes.c_int32),
                 ("stage_lds", ctypes.c_int32), ("prefetch", ctypes.c_int32),
                 ("schedule", ctypes.c_int32), ("reuse_sample", ctypes.c_int32),
-                ("out_degree", ctypes.c_int32), ("simple_graph", ctypes.c_int32)]
+                ("out_degree", ctypes.c_int32), ("simple_graph", ctypes.c_int32),
+                ("mfma_waves", ctypes.c_int32), ("mfma_ksteps", ctypes.c_int32),
+                ("hook_blocks", ctypes.c_int32)]
 
 
 class sng_stats(ctypes.Structure):
@@ -92,6 +95,14 @@ def load() -> ctypes.CDLL:
                          ctypes.c_int),
         "sng_autotune_lookup": ([P, i64, i32, i64, i64, cfgp], ctypes.c_int),
         "sng_autotune_clear": ([], ctypes.c_int),
+        "sng_autotune_lowp": ([P, i64, i32, i64, P, i64, f32, i32, dbl, dbl, i32, u64, P, P, P,
+                               sz, i32, cfgp, P, P, P], ctypes.c_int),
+        "sng_autotune_hook": ([P, i64, i32, i64, i64, dbl, u64, i32, P, P, P, sz, i32, cfgp, P,
+                               P, P], ctypes.c_int),
+        "sng_autotune_batch": ([i32, P, P, i32, P, P, P, P, P, P, P, P, sz, i32, cfgp, P, P, P],
+                               ctypes.c_int),
+        "sng_autotune_save": ([ctypes.c_char_p], ctypes.c_int),
+        "sng_autotune_load": ([ctypes.c_char_p], ctypes.c_int),
         "sng_sweep_workspace_size": ([i64, i32, i64, i32, i32, ctypes.POINTER(sz)],
                                      ctypes.c_int),
         "sng_dbscan_sweep": ([P, i64, i32, i64, dbl, P, i32, P, i32, u64, P, P, P, sz, cfgp, P],

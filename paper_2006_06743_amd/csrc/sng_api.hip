@@ -1,10 +1,13 @@
 // C ABI of libsng.so: argument validation, workspace layout and the launch
 // sequence of each entry point (declarations and contracts in sng.h).
 #include <math.h>
+#include <stdio.h>
 #include <string.h>
 
 #include <map>
 #include <mutex>
+#include <sstream>
+#include <string>
 #include <tuple>
 #include <vector>
 
@@ -200,6 +203,13 @@ int check_cfg(const sng_config *cfg)
         return SNG_EINVAL;
     if (cfg->simple_graph && (cfg->out_degree || cfg->reuse_sample))
         return SNG_EINVAL;  // one degree mode at a time; the table moves the sample
+    const int w = cfg->mfma_waves, k = cfg->mfma_ksteps, h = cfg->hook_blocks;
+    if (w != 0 && w != 1 && w != 2 && w != 4)
+        return SNG_EINVAL;
+    if (k != 0 && k != 4 && k != 8 && k != 16)
+        return SNG_EINVAL;
+    if (h != 0 && (h < 256 || h > 65536))
+        return SNG_EINVAL;
     return SNG_OK;
 }
 
@@ -250,16 +260,25 @@ hipError_t init_header(unsigned long long *cnt, uint64_t slots, double band, hip
 // ---------------------------------------------------------------------------
 constexpr int kPreferPartner = 3;  // internal schedule: partner blocks when they fit, else direct
 
+// Forms with tuned shapes of their own (the key's first field).
+enum TuneForm : int { kFormPlain = 0, kFormBf16 = 1, kFormFp16 = 2, kFormBatch = 3 };
+
 struct TuneKey {
-    int d, vec, lg_n, lg_m;
+    int form, d, vec, lg_n, lg_m;
     bool operator<(const TuneKey &o) const
     {
-        return std::tie(d, vec, lg_n, lg_m) < std::tie(o.d, o.vec, o.lg_n, o.lg_m);
+        return std::tie(form, d, vec, lg_n, lg_m) <
+               std::tie(o.form, o.d, o.vec, o.lg_n, o.lg_m);
     }
 };
 
 std::mutex g_tune_mu;
 std::map<TuneKey, sng_config> g_tune;
+
+// The cache file: this header line, then one entry per line.
+const char *const kTuneFileHeader = "sng-autotune 1";
+constexpr int kConfigFields = (int)(sizeof(sng_config) / sizeof(int32_t));
+static_assert(sizeof(sng_config) == 11 * sizeof(int32_t), "the file lists every field");
 
 int ceil_log2(uint64_t v)
 {
@@ -269,32 +288,43 @@ int ceil_log2(uint64_t v)
     return r;
 }
 
-TuneKey tune_key(const float *X, int32_t d, int64_t ld, int64_t n, int64_t m)
+TuneKey tune_key(const float *X, int32_t d, int64_t ld, int64_t n, int64_t m,
+                 int form = kFormPlain)
 {
     const int vec = ((uintptr_t)X % 16 == 0) && (ld % 4 == 0);
-    return TuneKey{d, vec, ceil_log2((uint64_t)n), ceil_log2((uint64_t)m)};
+    return TuneKey{form, d, vec, ceil_log2((uint64_t)n), ceil_log2((uint64_t)m)};
 }
 
 // No launch shape chosen by the caller (the degree modes are not launch choices).
 bool is_default_cfg(const sng_config *cfg)
 {
     return !cfg || (cfg->lanes_per_pair == 0 && cfg->chunks_per_wave == 0 && cfg->stage_lds == 0 &&
-                    cfg->prefetch == 0 && cfg->schedule == 0 && cfg->reuse_sample == 0);
+                    cfg->prefetch == 0 && cfg->schedule == 0 && cfg->reuse_sample == 0 &&
+                    cfg->mfma_waves == 0 && cfg->mfma_ksteps == 0 && cfg->hook_blocks == 0);
+}
+
+// The cached configuration of `key`, if any.
+bool tuned_entry(const TuneKey &key, sng_config *out)
+{
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    const auto it = g_tune.find(key);
+    if (it == g_tune.end())
+        return false;
+    *out = it->second;
+    return true;
 }
 
 // The configuration a call runs with: the caller's own, or for a call without
 // one the tuned configuration of its shape class if there is one. A tuned
 // partner-block schedule becomes a preference, so a workspace sized for
 // direct gathers still works.
-const sng_config *effective_cfg(const Inst &I, const sng_config *cfg, sng_config *buf)
+const sng_config *effective_cfg(const Inst &I, const sng_config *cfg, sng_config *buf,
+                                int form = kFormPlain)
 {
     if (!is_default_cfg(cfg))
         return cfg;
-    std::lock_guard<std::mutex> lock(g_tune_mu);
-    const auto it = g_tune.find(tune_key(I.X, I.d, I.ld, I.n, I.m));
-    if (it == g_tune.end())
+    if (!tuned_entry(tune_key(I.X, I.d, I.ld, I.n, I.m, form), buf))
         return cfg;
-    *buf = it->second;
     if (buf->schedule == 2)
         buf->schedule = kPreferPartner;
     buf->out_degree = cfg ? cfg->out_degree : 0;
@@ -385,8 +415,67 @@ int run_plain(Inst &I, const sng_config *cfg, bool labels_wanted, const BucketGe
         return SNG_OK;
     SNG_TRY(launch_core_init(I, st));
     if (I.m > 0)
-        SNG_TRY(launch_hook_mask(I, st));
+        SNG_TRY(launch_hook_mask(I, st, cfg ? (unsigned)cfg->hook_blocks : 0u));
     SNG_TRY(launch_finalize(I, st));
+    return SNG_OK;
+}
+
+// Mean ms of `trials` calls of run() on st after one warm-up call (HIP
+// events; synchronises st). run returns a status; the first failure is
+// returned as is.
+template <class Run>
+int time_calls(hipStream_t st, int trials, Run &&run, float *ms)
+{
+    int rc = run();
+    if (rc != SNG_OK)
+        return rc;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        return SNG_EHIP;
+    }
+    if (hipEventRecord(e0, st) != hipSuccess)
+        rc = SNG_EHIP;
+    for (int k = 0; k < trials && rc == SNG_OK; ++k)
+        rc = run();
+    float t = 0.0f;
+    if (rc == SNG_OK && (hipEventRecord(e1, st) != hipSuccess ||
+                         hipEventSynchronize(e1) != hipSuccess ||
+                         hipEventElapsedTime(&t, e0, e1) != hipSuccess))
+        rc = SNG_EHIP;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *ms = t / (float)trials;
+    return rc;
+}
+
+// Times every candidate with run(config) (a candidate that fails with
+// SNG_EINVAL or SNG_ENOTIMPL is skipped as not applicable) and keeps the
+// fastest in *best, its mean time in *best_ms and the number timed in
+// *tried (both may be null).
+template <class Run>
+int tune_candidates(const std::vector<sng_config> &cand, hipStream_t st, int trials, Run &&run,
+                    sng_config *best, float *best_ms, int32_t *tried)
+{
+    float best_t = -1.0f;
+    int n_tried = 0;
+    for (const sng_config &c : cand) {
+        float ms = 0.0f;
+        const int rc = time_calls(st, trials, [&]() { return run(c); }, &ms);
+        if (rc == SNG_EINVAL || rc == SNG_ENOTIMPL)
+            continue;
+        if (rc != SNG_OK)
+            return rc;
+        ++n_tried;
+        if (best_t < 0.0f || ms < best_t) {
+            best_t = ms;
+            *best = c;
+        }
+    }
+    if (tried) *tried = n_tried;
+    if (best_t < 0.0f)
+        return SNG_ENOTIMPL;
+    if (best_ms) *best_ms = best_t;
     return SNG_OK;
 }
 
@@ -404,6 +493,7 @@ const char *sng_status_string(int status)
     case SNG_EHIP: return "HIP runtime error";
     case SNG_EOVERFLOW: return "device queue overflow";
     case SNG_ENOTIMPL: return "not implemented for these arguments";
+    case SNG_EIO: return "file could not be opened, read or written";
     default: return "unknown status";
     }
 }
@@ -609,7 +699,10 @@ int sng_autotune(const float *X, int64_t n, int32_t d, int64_t ld, int64_t m, do
         return SNG_ENOTIMPL;
     if (best_ms) *best_ms = best_t;
     std::lock_guard<std::mutex> lock(g_tune_mu);
-    g_tune[tune_key(X, d, ld, n, m)] = *best;
+    sng_config &e = g_tune[tune_key(X, d, ld, n, m)];
+    const int32_t hook = e.hook_blocks;  // tuned separately (sng_autotune_hook)
+    e = *best;
+    e.hook_blocks = hook;
     return SNG_OK;
 }
 
@@ -633,9 +726,86 @@ int sng_autotune_clear(void)
     return SNG_OK;
 }
 
-int sng_cluster(const float *X, int64_t n, int32_t d, int64_t ld, int64_t m, double eps,
+int sng_autotune_save(const char *path)
+{
+    if (!path)
+        return SNG_EINVAL;
+    std::ostringstream out;
+    out << kTuneFileHeader << "\n";
+    {
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        for (const auto &kv : g_tune) {
+            const TuneKey &k = kv.first;
+            const int32_t *f = reinterpret_cast<const int32_t *>(&kv.second);
+            out << k.form << ' ' << k.d << ' ' << k.vec << ' ' << k.lg_n << ' ' << k.lg_m;
+            for (int i = 0; i < kConfigFields; ++i)
+                out << ' ' << f[i];
+            out << "\n";
+        }
+    }
+    FILE *fp = fopen(path, "w");
+    if (!fp)
+        return SNG_EIO;
+    const std::string text = out.str();
+    const bool ok = fwrite(text.data(), 1, text.size(), fp) == text.size();
+    return (fclose(fp) == 0 && ok) ? SNG_OK : SNG_EIO;
+}
+
+int sng_autotune_load(const char *path)
+{
+    if (!path)
+        return SNG_EINVAL;
+    FILE *fp = fopen(path, "r");
+    if (!fp)
+        return SNG_EIO;
+    std::string text;
+    char buf[4096];
+    size_t got;
+    while ((got = fread(buf, 1, sizeof(buf), fp)) > 0)
+        text.append(buf, got);
+    const bool read_ok = !ferror(fp);
+    fclose(fp);
+    if (!read_ok)
+        return SNG_EIO;
+    std::istringstream in(text);
+    std::string line;
+    if (!std::getline(in, line) || line != kTuneFileHeader)
+        return SNG_EINVAL;
+    std::map<TuneKey, sng_config> add;
+    while (std::getline(in, line)) {
+        if (line.empty())
+            continue;
+        std::istringstream ls(line);
+        TuneKey k;
+        sng_config c;
+        int32_t *f = reinterpret_cast<int32_t *>(&c);
+        if (!(ls >> k.form >> k.d >> k.vec >> k.lg_n >> k.lg_m))
+            return SNG_EINVAL;
+        for (int i = 0; i < kConfigFields; ++i)
+            if (!(ls >> f[i]))
+                return SNG_EINVAL;
+        std::string rest;
+        if (ls >> rest)
+            return SNG_EINVAL;  // trailing fields
+        if (k.form < kFormPlain || k.form > kFormBatch || k.d < 1 || k.vec < 0 || k.vec > 1 ||
+            k.lg_n < 0 || k.lg_n > 63 || k.lg_m < 0 || k.lg_m > 63 || check_cfg(&c) != SNG_OK)
+            return SNG_EINVAL;
+        add[k] = c;
+    }
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    for (const auto &kv : add)
+        g_tune[kv.first] = kv.second;
+    return SNG_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// sng_cluster with the hook grid given (0: the tuned or default one).
+int cluster_run(const float *X, int64_t n, int32_t d, int64_t ld, int64_t m, double eps,
                 uint64_t seed, int32_t min_pts, const uint32_t *degrees, int32_t *labels,
-                void *workspace, size_t ws_bytes, void *stream)
+                void *workspace, size_t ws_bytes, void *stream, unsigned hook_blocks)
 {
     int rc = check_points(X, n, d, ld);
     if (rc) return rc;
@@ -654,11 +824,62 @@ int sng_cluster(const float *X, int64_t n, int32_t d, int64_t ld, int64_t m, dou
     I.mask = cv.take<uint32_t>(sizes_for(n, m).chunks * 8);
     I.deg = const_cast<uint32_t *>(degrees);  // read only below
     I.labels = labels;
+    if (hook_blocks == 0) {
+        sng_config tuned;
+        if (tuned_entry(tune_key(X, d, ld, n, m), &tuned))
+            hook_blocks = (unsigned)tuned.hook_blocks;
+    }
     SNG_TRY(launch_fill_u64(I.cnt + kCntCore, 3, 0ull, st));  // core/cluster/noise counts
     SNG_TRY(launch_core_init(I, st));
     if (I.m > 0)
-        SNG_TRY(launch_hook_mask(I, st));
+        SNG_TRY(launch_hook_mask(I, st, hook_blocks));
     SNG_TRY(launch_finalize(I, st));
+    return SNG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sng_cluster(const float *X, int64_t n, int32_t d, int64_t ld, int64_t m, double eps,
+                uint64_t seed, int32_t min_pts, const uint32_t *degrees, int32_t *labels,
+                void *workspace, size_t ws_bytes, void *stream)
+{
+    return cluster_run(X, n, d, ld, m, eps, seed, min_pts, degrees, labels, workspace, ws_bytes,
+                       stream, 0u);
+}
+
+int sng_autotune_hook(const float *X, int64_t n, int32_t d, int64_t ld, int64_t m, double eps,
+                      uint64_t seed, int32_t min_pts, const uint32_t *degrees, int32_t *labels,
+                      void *workspace, size_t ws_bytes, int32_t trials, sng_config *best,
+                      float *best_ms, int32_t *tried, void *stream)
+{
+    if (!best || trials < 1 || trials > 1000) return SNG_EINVAL;
+    int rc = check_points(X, n, d, ld);
+    if (rc) return rc;
+    memset(best, 0, sizeof(*best));
+    if (best_ms) *best_ms = 0.0f;
+    if (tried) *tried = 0;
+    // grids around the default's cap of 4096 blocks of 256 threads
+    std::vector<sng_config> cand;
+    for (int b : {1024, 2048, 4096, 8192, 16384, 32768}) {
+        sng_config c;
+        memset(&c, 0, sizeof(c));
+        c.hook_blocks = b;
+        cand.push_back(c);
+    }
+    rc = tune_candidates(
+        cand, (hipStream_t)stream, trials,
+        [&](const sng_config &c) {
+            return cluster_run(X, n, d, ld, m, eps, seed, min_pts, degrees, labels, workspace,
+                               ws_bytes, stream, (unsigned)c.hook_blocks);
+        },
+        best, best_ms, tried);
+    if (rc != SNG_OK)
+        return rc;
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    sng_config &e = g_tune[tune_key(X, d, ld, n, m)];  // zero-initialised when new
+    e.hook_blocks = best->hook_blocks;
     return SNG_OK;
 }
 
@@ -815,13 +1036,60 @@ int sng_dbscan_lowp(const float *X, int64_t n, int32_t d, int64_t ld, const uint
     L.eps2_lo = (I.eps2 - beta64) / (1.0 + c) * (1.0 - 0x1p-50);
     L.eps2_hi = (I.eps2 + beta64) / (1.0 - c) * (1.0 + 0x1p-50);
     SNG_TRY(init_header(I.cnt, (uint64_t)n * (uint64_t)m, c, st));
+    sng_config tuned;
+    const sng_config *ec =
+        effective_cfg(I, cfg, &tuned, prec == SNG_BF16 ? kFormBf16 : kFormFp16);
     SNG_TRY(launch_fill_u32(I.deg, I.n, 0u, st));
     SNG_TRY(launch_fill_u32(I.mask, words, 0u, st));
-    SNG_TRY(launch_lowp(I, L, prec, st));
+    const hipError_t le =
+        launch_lowp(I, L, prec, st, ec ? ec->mfma_waves : 0, ec ? ec->mfma_ksteps : 0);
+    if (le == hipErrorInvalidValue && ec && ec->mfma_waves != 0)
+        return SNG_ENOTIMPL;  // the requested waves per block do not fit the LDS for this d
+    SNG_TRY(le);
     SNG_TRY(launch_core_init(I, st));
     if (I.m > 0)
-        SNG_TRY(launch_hook_mask(I, st));
+        SNG_TRY(launch_hook_mask(I, st, ec ? (unsigned)ec->hook_blocks : 0u));
     SNG_TRY(launch_finalize(I, st));
+    return SNG_OK;
+}
+
+int sng_autotune_lowp(const float *X, int64_t n, int32_t d, int64_t ld, const uint16_t *X_lp,
+                      int64_t ld_lp, float lp_scale, int32_t prec, double s, double eps,
+                      int32_t min_pts, uint64_t seed, int32_t *labels, uint32_t *degrees,
+                      void *workspace, size_t ws_bytes, int32_t trials, sng_config *best,
+                      float *best_ms, int32_t *tried, void *stream)
+{
+    if (!best || trials < 1 || trials > 1000) return SNG_EINVAL;
+    if (prec != SNG_BF16 && prec != SNG_FP16) return SNG_EINVAL;
+    int rc = check_points(X, n, d, ld);
+    if (rc) return rc;
+    int64_t m = 0;
+    if ((rc = m_from_s(s, n, &m))) return rc;
+    memset(best, 0, sizeof(*best));
+    if (best_ms) *best_ms = 0.0f;
+    if (tried) *tried = 0;
+    if (n == 0 || m == 0)
+        return SNG_OK;  // no sampled-distance pass to tune
+    std::vector<sng_config> cand;
+    for (int w : {4, 2, 1})
+        for (int k : {4, 8, 16}) {
+            sng_config c;
+            memset(&c, 0, sizeof(c));
+            c.mfma_waves = w;
+            c.mfma_ksteps = k;
+            cand.push_back(c);
+        }
+    rc = tune_candidates(
+        cand, (hipStream_t)stream, trials,
+        [&](const sng_config &c) {
+            return sng_dbscan_lowp(X, n, d, ld, X_lp, ld_lp, lp_scale, prec, s, eps, min_pts,
+                                   seed, labels, degrees, workspace, ws_bytes, &c, stream);
+        },
+        best, best_ms, tried);
+    if (rc != SNG_OK)
+        return rc;
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    g_tune[tune_key(X, d, ld, n, m, prec == SNG_BF16 ? kFormBf16 : kFormFp16)] = *best;
     return SNG_OK;
 }
 
@@ -1102,6 +1370,29 @@ int batch_upload(const BatchHost &h, hipStream_t st)
     return SNG_OK;
 }
 
+// A batch's autotune key: d, the row alignment of every instance, and
+// ceil(log2) of its largest n and m.
+TuneKey batch_key(const BatchHost &h)
+{
+    uint64_t mn = 0, mm = 0;
+    for (const Inst &I : h.insts) {
+        mn = I.n > mn ? I.n : mn;
+        mm = I.m > mm ? I.m : mm;
+    }
+    return TuneKey{kFormBatch, h.d, h.vec_ok ? 1 : 0, ceil_log2(mn), ceil_log2(mm)};
+}
+
+// The batched pass's launch shape: cfg's, else the tuned one, else the
+// defaults.
+PassAShape batch_shape(const BatchHost &h, const sng_config *cfg)
+{
+    sng_config t;
+    if (!cfg && tuned_entry(batch_key(h), &t))
+        cfg = &t;
+    return resolve_shape(h.d, h.vec_ok, cfg ? cfg->lanes_per_pair : 0,
+                         cfg ? cfg->chunks_per_wave : 0, 0, cfg ? cfg->prefetch : 0);
+}
+
 }  // namespace
 
 struct sng_batch_plan {
@@ -1140,8 +1431,62 @@ int sng_dbscan_batch(int32_t count, const float *const *X, const int64_t *n, int
     if (count == 0) return SNG_OK;
     hipStream_t st = (hipStream_t)stream;
     if ((rc = batch_upload(h, st))) return rc;
-    const PassAShape sh = resolve_shape(d, h.vec_ok, 0, 0, 0, 0);
+    const PassAShape sh = batch_shape(h, nullptr);
     SNG_TRY(launch_batch(h.dT, h.G, d, h.vec_ok, sh, st));
+    return SNG_OK;
+}
+
+int sng_autotune_batch(int32_t count, const float *const *X, const int64_t *n, int32_t d,
+                       const int64_t *ld, const double *s, const double *eps,
+                       const int32_t *min_pts, const uint64_t *seed, int32_t *const *labels,
+                       uint32_t *const *degrees, void *workspace, size_t ws_bytes, int32_t trials,
+                       sng_config *best, float *best_ms, int32_t *tried, void *stream)
+{
+    if (!best || trials < 1 || trials > 1000) return SNG_EINVAL;
+    BatchHost h;
+    int rc = batch_prepare(count, X, n, d, ld, s, eps, min_pts, seed, labels, degrees, workspace,
+                           ws_bytes, h);
+    if (rc) return rc;
+    memset(best, 0, sizeof(*best));
+    if (best_ms) *best_ms = 0.0f;
+    if (tried) *tried = 0;
+    if (count == 0) return SNG_OK;
+    hipStream_t st = (hipStream_t)stream;
+    if ((rc = batch_upload(h, st))) return rc;
+    // lanes per pair around the default, rows in flight, chunks per wave;
+    // shapes that resolve to the same launch are tried once
+    const int g0 = resolve_shape(d, h.vec_ok, 0, 0, 0, 0).lanes;
+    std::vector<sng_config> cand;
+    std::vector<std::tuple<int, int, int>> seen;
+    for (int g : {g0, g0 / 2, g0 * 2}) {
+        if (g < 1 || g > 64) continue;
+        for (int pf : {4, 8, 16})
+            for (int cpw : {4, 8, 16, 32}) {
+                const PassAShape sh = resolve_shape(d, h.vec_ok, g, cpw, 0, pf);
+                const auto key = std::make_tuple(sh.lanes, sh.chunks_per_wave, sh.owners_per_batch);
+                bool dup = false;
+                for (const auto &k : seen)
+                    dup = dup || k == key;
+                if (dup) continue;
+                seen.push_back(key);
+                sng_config c;
+                memset(&c, 0, sizeof(c));
+                c.lanes_per_pair = sh.lanes;
+                c.chunks_per_wave = sh.chunks_per_wave;
+                c.prefetch = 4 * sh.owners_per_batch;
+                cand.push_back(c);
+            }
+    }
+    rc = tune_candidates(
+        cand, st, trials,
+        [&](const sng_config &c) {
+            return hip_rc(launch_batch(h.dT, h.G, d, h.vec_ok, batch_shape(h, &c), st));
+        },
+        best, best_ms, tried);
+    if (rc != SNG_OK)
+        return rc;
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    g_tune[batch_key(h)] = *best;
     return SNG_OK;
 }
 
@@ -1164,7 +1509,7 @@ int sng_batch_plan_create(int32_t count, const float *const *X, const int64_t *n
         delete p;
         return SNG_EHIP;
     }
-    const PassAShape sh = resolve_shape(d, h.vec_ok, 0, 0, 0, 0);
+    const PassAShape sh = batch_shape(h, nullptr);
     bool ok = hipStreamBeginCapture(p->capture, hipStreamCaptureModeThreadLocal) == hipSuccess;
     hipError_t le = hipSuccess;
     if (ok)

@@ -140,11 +140,17 @@ hipError_t launch_core_init(const Inst &I, hipStream_t st)
     return hipGetLastError();
 }
 
-hipError_t launch_hook_mask(const Inst &I, hipStream_t st)
+hipError_t launch_hook_mask(const Inst &I, hipStream_t st, unsigned blocks)
 {
     if (I.chunks == 0)
         return hipSuccess;
-    hipLaunchKernelGGL(k_hook_mask, dim3(grid_for(I.chunks * 8ull, 256)), dim3(256), 0, st, I);
+    const uint64_t words = I.chunks * 8ull;
+    unsigned g = grid_for(words, 256);
+    if (blocks != 0) {  // a tuned grid (the loop is grid-stride), no more than one word per thread
+        const uint64_t most = (words + 255) / 256;
+        g = (unsigned)(blocks < most ? blocks : most);
+    }
+    hipLaunchKernelGGL(k_hook_mask, dim3(g), dim3(256), 0, st, I);
     return hipGetLastError();
 }
 

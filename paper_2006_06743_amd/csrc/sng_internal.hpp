@@ -36,7 +36,11 @@ struct LowpArgs {
     double tiny;           // absolute slack for flushed subnormals
 };
 
-hipError_t launch_lowp(const Inst &I, const LowpArgs &L, int prec, hipStream_t st);
+// waves: wavefronts per block of the MFMA pass (0: as many of 4, 2, 1 as
+// the LDS allows); ksteps: 32-wide K-steps of partner fragments loaded
+// together (0: 8). Shapes whose LDS does not fit return hipErrorInvalidValue.
+hipError_t launch_lowp(const Inst &I, const LowpArgs &L, int prec, hipStream_t st,
+                       int waves = 0, int ksteps = 0);
 
 // Sweep over a grid of eps (ascending) and MinPts values. The per-level
 // thresholds travel by value in the kernel arguments.
@@ -157,7 +161,8 @@ hipError_t launch_fill_u64(unsigned long long *p, uint64_t count, unsigned long 
 hipError_t launch_core_init(const Inst &I, hipStream_t st);
 hipError_t launch_compact(const int32_t *labels, uint32_t n, int32_t *out, int32_t *n_clusters,
                           hipStream_t st);
-hipError_t launch_hook_mask(const Inst &I, hipStream_t st);
+// blocks: the grid of the hook launch (0: the default).
+hipError_t launch_hook_mask(const Inst &I, hipStream_t st, unsigned blocks = 0);
 hipError_t launch_finalize(const Inst &I, hipStream_t st);
 hipError_t launch_edge_degrees(const int32_t *edges, int64_t n_edges, uint32_t *deg,
                                hipStream_t st);

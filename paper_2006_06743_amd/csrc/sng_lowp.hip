@@ -149,11 +149,11 @@ __device__ __forceinline__ f32x4 mfma16x16x32(u16x8 a, u16x8 b, f32x4 c)
                                                        __builtin_bit_cast(f16x8, b), c, 0, 0, 0);
 }
 
-constexpr int kKB = 8;  // K-steps of 32 whose partner fragments are in flight together
 
 // One wave per source point; 64 Philox calls (256 slots, 16 tiles) at a time.
 // LDS per wave: the source row (KS*32 16-bit values) and 256 partner indices.
-template <int PREC>
+// kKB: K-steps of 32 whose partner fragments are in flight together.
+template <int PREC, int kKB>
 __global__ __launch_bounds__(256) void k_lowp_pass_a(Inst I, LowpArgs L, int KS)
 {
     extern __shared__ uint16_t lds16[];
@@ -373,7 +373,8 @@ __global__ void k_lowp_count_rechecked(unsigned long long *cnt)
         cnt[kCntRechecked] = cnt[kCntQueue];
 }
 
-hipError_t launch_lowp(const Inst &I, const LowpArgs &L, int prec, hipStream_t st)
+hipError_t launch_lowp(const Inst &I, const LowpArgs &L, int prec, hipStream_t st, int waves_req,
+                       int ksteps)
 {
     if (I.n == 0 || I.m == 0)
         return hipSuccess;
@@ -382,6 +383,15 @@ hipError_t launch_lowp(const Inst &I, const LowpArgs &L, int prec, hipStream_t s
     int waves = 4;
     while (waves > 1 && lds_per_wave * waves > 65536)
         waves >>= 1;
+    if (waves_req != 0) {
+        if (waves_req != 1 && waves_req != 2 && waves_req != 4)
+            return hipErrorInvalidValue;
+        waves = waves_req;
+    }
+    if (ksteps == 0)
+        ksteps = 8;
+    if (ksteps != 4 && ksteps != 8 && ksteps != 16)
+        return hipErrorInvalidValue;
     if (lds_per_wave * waves > 65536)
         return hipErrorInvalidValue;
     const uint64_t sb = ((uint64_t)I.n + 3) / 4;
@@ -399,10 +409,18 @@ hipError_t launch_lowp(const Inst &I, const LowpArgs &L, int prec, hipStream_t s
     const uint64_t nb = ((uint64_t)I.n + waves - 1) / waves;
     const unsigned blocks = (unsigned)(nb < 8192 ? nb : 8192);
     const size_t lds = lds_per_wave * waves;
-    if (prec == 1)
-        hipLaunchKernelGGL(k_lowp_pass_a<1>, dim3(blocks), dim3(64 * waves), lds, st, I, L, KS);
-    else
-        hipLaunchKernelGGL(k_lowp_pass_a<2>, dim3(blocks), dim3(64 * waves), lds, st, I, L, KS);
+#define SNG_LOWP_LAUNCH(P, KB)                                                                 \
+    hipLaunchKernelGGL((k_lowp_pass_a<P, KB>), dim3(blocks), dim3(64 * waves), lds, st, I, L, KS)
+    if (prec == 1) {
+        if (ksteps == 4) SNG_LOWP_LAUNCH(1, 4);
+        else if (ksteps == 8) SNG_LOWP_LAUNCH(1, 8);
+        else SNG_LOWP_LAUNCH(1, 16);
+    } else {
+        if (ksteps == 4) SNG_LOWP_LAUNCH(2, 4);
+        else if (ksteps == 8) SNG_LOWP_LAUNCH(2, 8);
+        else SNG_LOWP_LAUNCH(2, 16);
+    }
+#undef SNG_LOWP_LAUNCH
     if ((e = hipGetLastError()) != hipSuccess)
         return e;
     hipLaunchKernelGGL(k_lowp_recheck, dim3(1024), dim3(kWave * kRecheckWaves), 0, st, I, L);

@@ -247,9 +247,10 @@ def test_sweep_limits_as_documented(lib):
 def test_config_round_trip_keeps_every_field():
     import paper_2006_06743_amd as sng
     from paper_2006_06743_amd._lib import sng_config
-    c = sng_config(4, 8, 1, 16, 2, 1, 1, 1)
+    c = sng_config(4, 8, 1, 16, 2, 1, 1, 1, 2, 16, 8192)
     back = sng._config_of(c)
-    assert back == sng.Config(4, 8, 1, 16, 2, 1, 1, 1)
+    assert back == sng.Config(4, 8, 1, 16, 2, 1, 1, 1, 2, 16, 8192)
+    assert ctypes.sizeof(sng_config) == 11 * 4
 
 
 def test_noalloc_limits_before_any_device_work(lib):
@@ -268,3 +269,81 @@ def test_noalloc_limits_before_any_device_work(lib):
     reuse = sng_config(0, 0, 0, 0, 0, 1, 0, 0)
     assert lib.sng_dbscan_noalloc(fake, 10, 2, 2, 0.5, 1.0, 3, 1, lab, None,
                                   ctypes.byref(reuse), None) == -1
+
+
+def test_tuned_shape_fields_are_validated(lib):
+    """mfma_waves, mfma_ksteps and hook_blocks take the documented values
+    only; a bad one is rejected before any device work."""
+    from paper_2006_06743_amd._lib import sng_config
+    fake = ctypes.c_void_p(0x1000)
+    lab = ctypes.c_void_p(0x3000)
+    for field, bad in [("mfma_waves", 3), ("mfma_waves", 8), ("mfma_ksteps", 2),
+                       ("mfma_ksteps", 32), ("hook_blocks", 255), ("hook_blocks", 65537),
+                       ("hook_blocks", -1)]:
+        c = sng_config()
+        setattr(c, field, bad)
+        assert lib.sng_dbscan(fake, 10, 2, 2, 0.5, 0.1, 3, 1, lab, None, fake, 10**9,
+                              ctypes.byref(c), None) == -1, (field, bad)
+
+
+def test_tuners_reject_bad_arguments_before_launch(lib):
+    from paper_2006_06743_amd._lib import sng_config
+    fake = ctypes.c_void_p(0x1000)
+    best = sng_config()
+    # trials out of range, no output
+    for trials, out in [(0, ctypes.byref(best)), (1001, ctypes.byref(best)), (2, None)]:
+        assert lib.sng_autotune_lowp(fake, 10, 2, 2, fake, 8, 1.0, 1, 0.5, 0.1, 3, 1, fake, None,
+                                     fake, 10**9, trials, out, None, None, None) == -1
+        assert lib.sng_autotune_hook(fake, 10, 2, 2, 5, 0.1, 1, 3, fake, fake, fake, 10**9,
+                                     trials, out, None, None, None) == -1
+        assert lib.sng_autotune_batch(0, None, None, 2, None, None, None, None, None, None,
+                                      None, fake, 10**9, trials, out, None, None, None) == -1
+    # a precision the mixed form does not have
+    assert lib.sng_autotune_lowp(fake, 10, 2, 2, fake, 8, 1.0, 0, 0.5, 0.1, 3, 1, fake, None,
+                                 fake, 10**9, 2, ctypes.byref(best), None, None, None) == -1
+    # an empty batch: nothing to tune, an all-zero config
+    assert lib.sng_autotune_batch(0, None, None, 2, None, None, None, None, None, None, None,
+                                  fake, 10**9, 2, ctypes.byref(best), None, None, None) == 0
+    assert best.lanes_per_pair == 0 and best.prefetch == 0
+
+
+def _entry(form, d, vec, lg_n, lg_m, fields):
+    return " ".join(str(v) for v in [form, d, vec, lg_n, lg_m] + list(fields))
+
+
+def test_autotune_cache_file_round_trip(lib, tmp_path):
+    """A cache file loads into the cache (plain entries are found by lookup),
+    saves back to the same text, and bad files change nothing."""
+    from paper_2006_06743_amd._lib import sng_config
+    fake = ctypes.c_void_p(0x1000)  # 16-byte aligned
+    plain = _entry(0, 2, 1, 4, 3, [1, 8, 0, 8, 1, 0, 0, 0, 0, 0, 4096])
+    bf16 = _entry(1, 784, 1, 17, 10, [0, 0, 0, 0, 0, 0, 0, 0, 2, 16, 0])
+    batch = _entry(3, 3, 1, 18, 11, [1, 16, 0, 8, 0, 0, 0, 0, 0, 0, 0])
+    good = tmp_path / "tune.txt"
+    good.write_text("sng-autotune 1\n" + "\n".join([plain, bf16, batch]) + "\n")
+    assert lib.sng_autotune_clear() == 0
+    assert lib.sng_autotune_load(str(good).encode()) == 0
+    out = sng_config()
+    # n = 10 -> ceil(log2) 4, m = 5 -> 3, d = 2, ld = 4 (16-byte rows)
+    assert lib.sng_autotune_lookup(fake, 10, 2, 4, 5, ctypes.byref(out)) == 0
+    assert (out.lanes_per_pair, out.chunks_per_wave, out.prefetch, out.schedule,
+            out.hook_blocks) == (1, 8, 8, 1, 4096)
+    back = tmp_path / "back.txt"
+    assert lib.sng_autotune_save(str(back).encode()) == 0
+    assert back.read_text().splitlines() == ["sng-autotune 1", plain, bf16, batch]
+    # bad files: nothing changes
+    for text in ["sng-autotune 2\n" + plain + "\n",                         # version
+                 "sng-autotune 1\n" + plain[:-5] + "\n",                     # short line
+                 "sng-autotune 1\n" + plain + " 7\n",                        # trailing field
+                 "sng-autotune 1\n" + _entry(0, 2, 1, 4, 3, [3] + [0] * 10) + "\n",  # lanes 3
+                 "sng-autotune 1\n" + _entry(4, 2, 1, 4, 3, [0] * 11) + "\n",        # form 4
+                 "sng-autotune 1\n" + _entry(0, 2, 1, 4, 3, [0] * 10 + [100]) + "\n"]:
+        bad = tmp_path / "bad.txt"
+        bad.write_text(text)
+        assert lib.sng_autotune_clear() == 0
+        assert lib.sng_autotune_load(str(bad).encode()) == -1, text
+        assert lib.sng_autotune_lookup(fake, 10, 2, 4, 5, ctypes.byref(out)) == -6
+    assert lib.sng_autotune_load(str(tmp_path / "missing.txt").encode()) == -7
+    assert lib.sng_autotune_save(str(tmp_path / "no_dir" / "x.txt").encode()) == -7
+    assert lib.sng_autotune_load(None) == -1 and lib.sng_autotune_save(None) == -1
+    assert lib.sng_autotune_clear() == 0

@@ -176,3 +176,32 @@ def test_sweep_out_degree(sng, orc, schedule):
         for pi, mp in enumerate(mps):
             ref = orc.dbscan(X, e, mp, seed, s=s, out_degree=True)
             assert_same(L[pi, ki], D[ki], ref, "eps=%g MinPts=%d" % (e, mp))
+
+
+def test_autotune_batch_and_tuned_batches(sng, orc, tmp_path):
+    """The batch tuner times its launch shapes on a batch (every candidate's
+    results are the oracle's), caches the fastest under the batch's shape
+    class, and batch() and BatchPlan then run with it."""
+    import torch
+    rng = np.random.default_rng(41)
+    B = random_batch(rng, 20)
+    Xs = [gpu(b.X) for b in B]
+    args = ([b.s for b in B], [b.eps for b in B], [b.min_pts for b in B], [b.seed for b in B])
+    sng.autotune_clear()
+    print("autotune batch", flush=True)
+    best, ms, tried, labels, degs = sng.autotune_batch(Xs, *args, trials=1)
+    torch.cuda.synchronize()
+    assert tried >= 2 and ms > 0.0 and best.lanes_per_pair >= 1
+    check_batch(orc, B, labels, degs, "last candidate")
+    path = tmp_path / "tune.txt"
+    sng.autotune_save(str(path))
+    lines = path.read_text().splitlines()
+    assert lines[0] == "sng-autotune 1" and len(lines) == 2 and lines[1].startswith("3 ")
+    labels, degs, _ = sng.batch(Xs, *args)
+    torch.cuda.synchronize()
+    check_batch(orc, B, labels, degs, "tuned batch")
+    plan = sng.BatchPlan(Xs, *args)
+    labels, degs = plan.launch()
+    torch.cuda.synchronize()
+    check_batch(orc, B, labels, degs, "tuned plan")
+    sng.autotune_clear()

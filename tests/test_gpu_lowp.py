@@ -234,3 +234,40 @@ def test_filter_bound_is_reported_and_respected(sng, orc, prec):
     torch.cuda.synchronize()
     st2 = sng.stats(ws2)
     assert st2.filter_gamma == 0.0 and st2.filter_rel_width == 0.0
+
+
+@pytest.mark.parametrize("prec", [1, 2], ids=["bf16", "fp16"])
+def test_autotune_lowp_and_tuned_calls(sng, orc, prec, tmp_path):
+    """The mixed form's tuner times waves per block x K-steps in flight
+    (whole calls, each equal to the oracle), caches the fastest under its
+    precision, and a call without a config then runs with it."""
+    import torch
+    W = wl.mnistlike_784d(n_per=300)
+    X = W.X
+    bits = bits_for(X, prec)
+    s, eps = 0.05, 3.9
+    ref = orc.dbscan(X, eps, W.min_pts, W.seed, s=s)
+    Xg = torch.from_numpy(np.ascontiguousarray(X)).cuda()
+    sng.autotune_clear()
+    print("autotune lowp", prec, flush=True)
+    best, ms, tried, lab, deg = sng.autotune_lowp(Xg, lp_tensor(bits), s, eps, W.min_pts,
+                                                  W.seed, prec=prec, trials=1)
+    torch.cuda.synchronize()
+    assert tried == 9 and ms > 0.0
+    assert best.mfma_waves in (1, 2, 4) and best.mfma_ksteps in (4, 8, 16)
+    assert_same(lab.cpu().numpy(), deg.cpu().numpy().view(np.uint32), ref, "last candidate")
+    path = tmp_path / "tune.txt"
+    sng.autotune_save(str(path))
+    lines = path.read_text().splitlines()
+    assert len(lines) == 2 and lines[1].startswith("%d 784 " % prec)
+    gl, gd, _ = run_lowp(sng, X, bits, s, eps, W.min_pts, W.seed, prec)
+    assert_same(gl, gd, ref, "tuned call")
+    # every shape explicitly, against the oracle
+    for w in (1, 2, 4):
+        for k in (4, 8, 16):
+            lab, deg, _ = sng.dbscan_lowp(Xg, lp_tensor(bits), s, eps, W.min_pts, W.seed,
+                                          prec=prec, cfg=sng.Config(mfma_waves=w, mfma_ksteps=k))
+            torch.cuda.synchronize()
+            assert_same(lab.cpu().numpy(), deg.cpu().numpy().view(np.uint32), ref,
+                        "waves %d ksteps %d" % (w, k))
+    sng.autotune_clear()

@@ -427,6 +427,37 @@ def test_autotune_and_tuned_calls(sng, orc, n, d, s):
     assert sng.autotune_lookup(Xg, m) is None
 
 
+def test_autotune_hook_and_tuned_post_processing(sng, orc):
+    """The hook tuner times grids of the hook launch on a prepared
+    post-processing (each candidate's labels are the oracle's) and stores the
+    fastest in the plain entry of the shape class, which dbscan and cluster
+    then use."""
+    import torch
+    W = wl.mixture_16d(sigma=0.25, n_total=60_000)
+    m = orc.samples_per_point(0.02, W.n)
+    ref = orc.dbscan(W.X, W.eps, W.min_pts, W.seed, m=m)
+    Xg = torch.from_numpy(W.X).cuda()
+    sng.autotune_clear()
+    deg, ws = sng.degrees(Xg, m, W.eps, W.seed)
+    print("autotune hook", flush=True)
+    best, ms, tried, lab = sng.autotune_hook(Xg, m, W.eps, W.seed, W.min_pts, deg, ws, trials=1)
+    torch.cuda.synchronize()
+    assert tried == 6 and ms > 0.0 and 1024 <= best.hook_blocks <= 32768
+    assert np.array_equal(lab.cpu().numpy(), ref.labels)
+    tuned = sng.autotune_lookup(Xg, m)
+    assert tuned is not None and tuned.hook_blocks == best.hook_blocks
+    assert tuned.lanes_per_pair == 0 and tuned.schedule == 0  # pass fields stay default
+    lab = sng.cluster(Xg, m, W.eps, W.seed, W.min_pts, deg, ws)
+    torch.cuda.synchronize()
+    assert np.array_equal(lab.cpu().numpy(), ref.labels)
+    gl, gd, _ = run(sng, W.X, 0.02, W.eps, W.min_pts, W.seed)
+    assert_same(gl, gd, ref, "tuned hook grid")
+    for hb in (256, 300, 65536):
+        gl, gd, _ = run(sng, W.X, 0.02, W.eps, W.min_pts, W.seed, cfg=sng.Config(hook_blocks=hb))
+        assert_same(gl, gd, ref, "hook_blocks %d" % hb)
+    sng.autotune_clear()
+
+
 def test_graph_deep_forests(sng):
     """Long paths hooked in random edge order build deep union-find trees;
     every core label must still be its component's minimum index (the final
