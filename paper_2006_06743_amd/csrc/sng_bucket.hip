@@ -99,7 +99,22 @@ __global__ __launch_bounds__(kGenThreads) void k_bkt_generate(Inst I, BucketGeom
     uint32_t *cp = lds_u32;                         // [2 gen_pairs(NJ)]: count, offset
     uint32_t *stage = lds_u32 + 2 * gen_pairs(NJ);  // [kRangeSlots]
     const uint32_t tid = threadIdx.x;
-    const uint64_t r = blockIdx.x;
+    // Persistent: one workgroup per compute unit walks ranges blockIdx.x,
+    // blockIdx.x + gridDim.x, ...; the sorted records of a range are copied
+    // out of the stage while the next range is counted (the stage is only
+    // written again after that count).
+    uint32_t *prev_dst = nullptr;  // the previous range's records, still in the stage
+    uint32_t prev_total = 0;
+    // This thread's 16-byte piece c of the previous range. The last piece
+    // may carry up to three stale words past the records; they land inside
+    // the range's own region, where nothing reads them.
+    auto copy_piece = [&](uint32_t c) {
+        const uint32_t k = 4 * (tid + c * kGenThreads);
+        if (k < prev_total)
+            *reinterpret_cast<uint4 *>(prev_dst + k) = *reinterpret_cast<const uint4 *>(stage + k);
+    };
+    static_assert(4 * kGenThreads * kCallsPerThread == kRangeSlots, "one piece per call step");
+    for (uint64_t r = blockIdx.x; r < B.ranges; r += gridDim.x) {
     const uint64_t call_lo = r * kRangeCalls;
     const uint64_t call_hi = min(call_lo + kRangeCalls, I.calls);
     const uint32_t ncalls = (uint32_t)(call_hi - call_lo);
@@ -176,6 +191,12 @@ __global__ __launch_bounds__(kGenThreads) void k_bkt_generate(Inst I, BucketGeom
                 ++ii;
                 hb += cH;
             }
+            // two pieces per step in the first half of the count, while few
+            // records are held in registers
+            if (prev_dst && c < kCallsPerThread / 2) {
+                copy_piece(2 * c);
+                copy_piece(2 * c + 1);
+            }
         }
     };
     if (ncalls == kRangeCalls && (I.m & 3u) == 0)
@@ -209,14 +230,13 @@ __global__ __launch_bounds__(kGenThreads) void k_bkt_generate(Inst I, BucketGeom
         stage[base + (key[k] & 0xFFFFu)] = rec[k];
     }
     __syncthreads();
-    uint32_t *dst = B.rec + r * B.region;
-    for (uint32_t k = 4 * tid; k < total; k += 4 * kGenThreads) {
-        if (k + 4 <= total) {
-            *reinterpret_cast<uint4 *>(dst + k) = *reinterpret_cast<const uint4 *>(stage + k);
-        } else {
-            for (uint32_t e = k; e < total; ++e)
-                dst[e] = stage[e];
-        }
+    prev_dst = B.rec + r * B.region;
+    prev_total = total;
+    }
+    if (prev_dst) {
+#pragma unroll
+        for (uint32_t c = 0; c < kCallsPerThread; ++c)
+            copy_piece(c);
     }
 }
 
@@ -355,7 +375,8 @@ hipError_t launch_bucket_generate(const Inst &I, const BucketGeom &B, hipStream_
     hipLaunchKernelGGL(k_bkt_prepare, dim3(1), dim3(64), 0, st, B, 1);
     const size_t lds = ((size_t)kRangeSlots + 2 * (size_t)gen_pairs(B.NJ)) * sizeof(uint32_t);
     const float inv_lo = gen_inv_lo(I.n);
-    const dim3 grid((unsigned)B.ranges), block(kGenThreads);
+    const unsigned cus = lds_eval_blocks();
+    const dim3 grid((unsigned)(B.ranges < cus ? B.ranges : cus)), block(kGenThreads);
     if (inv_lo != 0.0f)
         hipLaunchKernelGGL(k_bkt_generate<3>, grid, block, lds, st, I, B, inv_lo);
     else if (I.inv_nf != 0.0f && I.n < (1u << 24))
