@@ -115,123 +115,123 @@ __global__ __launch_bounds__(kGenThreads) void k_bkt_generate(Inst I, BucketGeom
     };
     static_assert(4 * kGenThreads * kCallsPerThread == kRangeSlots, "one piece per call step");
     for (uint64_t r = blockIdx.x; r < B.ranges; r += gridDim.x) {
-    const uint64_t call_lo = r * kRangeCalls;
-    const uint64_t call_hi = min(call_lo + kRangeCalls, I.calls);
-    const uint32_t ncalls = (uint32_t)(call_hi - call_lo);
-    const uint32_t i0 = (uint32_t)(call_lo / I.C);
-    const uint32_t c0 = (uint32_t)(call_lo - (uint64_t)i0 * I.C);
-    for (uint32_t k = tid; k < 2 * gen_pairs(NJ); k += kGenThreads)
-        cp[k] = 0;
-    if (tid == 0) {
-        B.start[2 * r + 0] = i0;  // source and call of the range's first call
-        B.start[2 * r + 1] = c0;
-    }
-    __syncthreads();
-    // this thread's calls are c0 + tid + k * kGenThreads of the range: the
-    // first split into (source, call within the point) by one division, the
-    // next ones advanced by kGenThreads = step_q * C + step_r calls
-    uint32_t cc = c0 + tid, ii = i0;
-    if (cc >= I.C) {
-        const uint32_t q = div_exact(cc, I.C, I.inv_C);
-        ii += q;
-        cc -= q * I.C;
-    }
-    const uint32_t step_q = kGenThreads / I.C;
-    const uint32_t step_r = kGenThreads - step_q * I.C;
-    // The record's bits above its word and partner fields: the call offset
-    // in the range, or for LDS blocks (source offset in the range, call
-    // within the point). Both advance by dH per call, and the second by cH
-    // more when the call within the point wraps to the next source.
-    uint32_t hb, dH, cH;
-    const uint32_t w_shift = B.lds ? B.bshift : 16u;
-    if (B.lds) {
-        const uint32_t s = B.bshift + 2;
-        hb = (((ii - i0) << B.tc_bits) | cc) << s;
-        dH = ((step_q << B.tc_bits) + step_r) << s;
-        cH = ((1u << B.tc_bits) - I.C) << s;
-    } else {
-        hb = tid << kRecOffShift;
-        dH = kGenThreads << kRecOffShift;
-        cH = 0;
-    }
-    // word w of a call is a sample iff 4 cc + w < m; calls past the range
-    // get a call index no word passes
-    uint32_t thr[4];
-#pragma unroll
-    for (int w = 0; w < 4; ++w)
-        thr[w] = I.m > (uint32_t)w ? I.m - (uint32_t)w : 0u;
-    const uint32_t pmask = (1u << B.bshift) - 1u;
-    // key: byte offset of the block's pair << 16 | rank of the record in it
-    uint32_t key[4 * kCallsPerThread], rec[4 * kCallsPerThread];
-    // kAll: every call of the range is live and has four samples (m is a
-    // multiple of 4), so only self pairs make no record
-    auto count = [&]<bool kAll>() {
-#pragma unroll
-        for (uint32_t c = 0; c < kCallsPerThread; ++c) {
-            const bool live = kAll || tid < ncalls - min(ncalls, c * kGenThreads);
-            const uint32_t cc4 = live ? 4u * cc : 0xFFFFFFF0u;
-            const Words4 W = philox10(cc, ii, I.key0, I.key1);
-#pragma unroll
-            for (int w = 0; w < 4; ++w) {
-                const uint32_t j = kMod == 3   ? mod_f32_floor(W.w[w], I.n, inv_lo)
-                                   : kMod == 2 ? mod_f32_n24(W.w[w], I.n, I.inv_nf)
-                                   : kMod == 1 ? mod_f32(W.w[w], I.n, I.inv_nf)
-                                               : mod_exact(W.w[w], I.n, I.inv_n);
-                const bool none = (j == ii) | (!kAll && cc4 >= thr[w]);
-                const uint32_t J = none ? NJ : (j >> B.bshift);
-                const uint32_t rank = atomicAdd(cp + 2 * J, 1u);
-                key[4 * c + w] = (J << 19) | rank;
-                rec[4 * c + w] = (j & pmask) | hb | ((uint32_t)w << w_shift);
-            }
-            cc += step_r;
-            ii += step_q;
-            hb += dH;
-            if (cc >= I.C) {
-                cc -= I.C;
-                ++ii;
-                hb += cH;
-            }
-            // two pieces per step in the first half of the count, while few
-            // records are held in registers
-            if (prev_dst && c < kCallsPerThread / 2) {
-                copy_piece(2 * c);
-                copy_piece(2 * c + 1);
-            }
+        const uint64_t call_lo = r * kRangeCalls;
+        const uint64_t call_hi = min(call_lo + kRangeCalls, I.calls);
+        const uint32_t ncalls = (uint32_t)(call_hi - call_lo);
+        const uint32_t i0 = (uint32_t)(call_lo / I.C);
+        const uint32_t c0 = (uint32_t)(call_lo - (uint64_t)i0 * I.C);
+        for (uint32_t k = tid; k < 2 * gen_pairs(NJ); k += kGenThreads)
+            cp[k] = 0;
+        if (tid == 0) {
+            B.start[2 * r + 0] = i0;  // source and call of the range's first call
+            B.start[2 * r + 1] = c0;
         }
-    };
-    if (ncalls == kRangeCalls && (I.m & 3u) == 0)
-        count.template operator()<true>();
-    else
-        count.template operator()<false>();
-    __syncthreads();
-    const uint32_t v = tid < NJ ? cp[2 * tid] : 0u;
-    uint32_t total;
-    const uint32_t ex = gen_exclusive(v, wsum, &total);
-    if (tid < NJ) {
-        cp[2 * tid + 1] = ex;
-        *reinterpret_cast<uint2 *>(B.seg + (r * NJ + tid) * 2) = make_uint2(ex, v);
-    }
-    if (tid == 0) {
-        // the slots without a record go past the records
-        cp[2 * NJ + 1] = total;
-        // self pairs: the range's sample slots (words below m of its calls;
-        // the last call of a point has m - 4 (C - 1) of them) less its records
-        const uint32_t wraps = (c0 + ncalls) / I.C;  // points whose last call is in the range
-        const uint64_t slots = 4ull * ncalls - (uint64_t)(4u * I.C - I.m) * wraps;
-        const uint64_t self = slots - total;
-        if (self)
-            atomicAdd(B.hdr + 1, (unsigned long long)self);
-    }
-    __syncthreads();
-    const char *cpb = reinterpret_cast<const char *>(cp);
+        __syncthreads();
+        // this thread's calls are c0 + tid + k * kGenThreads of the range: the
+        // first split into (source, call within the point) by one division, the
+        // next ones advanced by kGenThreads = step_q * C + step_r calls
+        uint32_t cc = c0 + tid, ii = i0;
+        if (cc >= I.C) {
+            const uint32_t q = div_exact(cc, I.C, I.inv_C);
+            ii += q;
+            cc -= q * I.C;
+        }
+        const uint32_t step_q = kGenThreads / I.C;
+        const uint32_t step_r = kGenThreads - step_q * I.C;
+        // The record's bits above its word and partner fields: the call offset
+        // in the range, or for LDS blocks (source offset in the range, call
+        // within the point). Both advance by dH per call, and the second by cH
+        // more when the call within the point wraps to the next source.
+        uint32_t hb, dH, cH;
+        const uint32_t w_shift = B.lds ? B.bshift : 16u;
+        if (B.lds) {
+            const uint32_t s = B.bshift + 2;
+            hb = (((ii - i0) << B.tc_bits) | cc) << s;
+            dH = ((step_q << B.tc_bits) + step_r) << s;
+            cH = ((1u << B.tc_bits) - I.C) << s;
+        } else {
+            hb = tid << kRecOffShift;
+            dH = kGenThreads << kRecOffShift;
+            cH = 0;
+        }
+        // word w of a call is a sample iff 4 cc + w < m; calls past the range
+        // get a call index no word passes
+        uint32_t thr[4];
 #pragma unroll
-    for (uint32_t k = 0; k < 4 * kCallsPerThread; ++k) {
-        const uint32_t base = *reinterpret_cast<const uint32_t *>(cpb + (key[k] >> 16) + 4);
-        stage[base + (key[k] & 0xFFFFu)] = rec[k];
-    }
-    __syncthreads();
-    prev_dst = B.rec + r * B.region;
-    prev_total = total;
+        for (int w = 0; w < 4; ++w)
+            thr[w] = I.m > (uint32_t)w ? I.m - (uint32_t)w : 0u;
+        const uint32_t pmask = (1u << B.bshift) - 1u;
+        // key: byte offset of the block's pair << 16 | rank of the record in it
+        uint32_t key[4 * kCallsPerThread], rec[4 * kCallsPerThread];
+        // kAll: every call of the range is live and has four samples (m is a
+        // multiple of 4), so only self pairs make no record
+        auto count = [&]<bool kAll>() {
+#pragma unroll
+            for (uint32_t c = 0; c < kCallsPerThread; ++c) {
+                const bool live = kAll || tid < ncalls - min(ncalls, c * kGenThreads);
+                const uint32_t cc4 = live ? 4u * cc : 0xFFFFFFF0u;
+                const Words4 W = philox10(cc, ii, I.key0, I.key1);
+#pragma unroll
+                for (int w = 0; w < 4; ++w) {
+                    const uint32_t j = kMod == 3   ? mod_f32_floor(W.w[w], I.n, inv_lo)
+                                       : kMod == 2 ? mod_f32_n24(W.w[w], I.n, I.inv_nf)
+                                       : kMod == 1 ? mod_f32(W.w[w], I.n, I.inv_nf)
+                                                   : mod_exact(W.w[w], I.n, I.inv_n);
+                    const bool none = (j == ii) | (!kAll && cc4 >= thr[w]);
+                    const uint32_t J = none ? NJ : (j >> B.bshift);
+                    const uint32_t rank = atomicAdd(cp + 2 * J, 1u);
+                    key[4 * c + w] = (J << 19) | rank;
+                    rec[4 * c + w] = (j & pmask) | hb | ((uint32_t)w << w_shift);
+                }
+                cc += step_r;
+                ii += step_q;
+                hb += dH;
+                if (cc >= I.C) {
+                    cc -= I.C;
+                    ++ii;
+                    hb += cH;
+                }
+                // two pieces per step in the first half of the count, while few
+                // records are held in registers
+                if (prev_dst && c < kCallsPerThread / 2) {
+                    copy_piece(2 * c);
+                    copy_piece(2 * c + 1);
+                }
+            }
+        };
+        if (ncalls == kRangeCalls && (I.m & 3u) == 0)
+            count.template operator()<true>();
+        else
+            count.template operator()<false>();
+        __syncthreads();
+        const uint32_t v = tid < NJ ? cp[2 * tid] : 0u;
+        uint32_t total;
+        const uint32_t ex = gen_exclusive(v, wsum, &total);
+        if (tid < NJ) {
+            cp[2 * tid + 1] = ex;
+            *reinterpret_cast<uint2 *>(B.seg + (r * NJ + tid) * 2) = make_uint2(ex, v);
+        }
+        if (tid == 0) {
+            // the slots without a record go past the records
+            cp[2 * NJ + 1] = total;
+            // self pairs: the range's sample slots (words below m of its calls;
+            // the last call of a point has m - 4 (C - 1) of them) less its records
+            const uint32_t wraps = (c0 + ncalls) / I.C;  // points whose last call is in the range
+            const uint64_t slots = 4ull * ncalls - (uint64_t)(4u * I.C - I.m) * wraps;
+            const uint64_t self = slots - total;
+            if (self)
+                atomicAdd(B.hdr + 1, (unsigned long long)self);
+        }
+        __syncthreads();
+        const char *cpb = reinterpret_cast<const char *>(cp);
+#pragma unroll
+        for (uint32_t k = 0; k < 4 * kCallsPerThread; ++k) {
+            const uint32_t base = *reinterpret_cast<const uint32_t *>(cpb + (key[k] >> 16) + 4);
+            stage[base + (key[k] & 0xFFFFu)] = rec[k];
+        }
+        __syncthreads();
+        prev_dst = B.rec + r * B.region;
+        prev_total = total;
     }
     if (prev_dst) {
 #pragma unroll
