@@ -314,9 +314,9 @@ bool bucket_geometry(int64_t n, int d, int64_t m, bool force, BucketGeom *g)
     return true;
 }
 
-unsigned lds_eval_blocks()
+unsigned compute_units()
 {
-    // one workgroup per compute unit of the current device (256 on MI355X)
+    // cached per device (256 on MI355X); racing first calls store the same value
     static int cus[64];
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64)
@@ -375,7 +375,7 @@ hipError_t launch_bucket_generate(const Inst &I, const BucketGeom &B, hipStream_
     hipLaunchKernelGGL(k_bkt_prepare, dim3(1), dim3(64), 0, st, B, 1);
     const size_t lds = ((size_t)kRangeSlots + 2 * (size_t)gen_pairs(B.NJ)) * sizeof(uint32_t);
     const float inv_lo = gen_inv_lo(I.n);
-    const unsigned cus = lds_eval_blocks();
+    const unsigned cus = compute_units();
     const dim3 grid((unsigned)(B.ranges < cus ? B.ranges : cus)), block(kGenThreads);
     if (inv_lo != 0.0f)
         hipLaunchKernelGGL(k_bkt_generate<3>, grid, block, lds, st, I, B, inv_lo);

@@ -773,9 +773,10 @@ inline bool lane_rows_fit(const Inst &I)
     return (((uint64_t)I.C - 1 + kRangeCalls - 1) / I.C + 1) * (uint64_t)I.d <= (uint64_t)kWave;
 }
 
-// Workgroups of the LDS form: one per compute unit (a block of up to
-// kLdsBlockBytes leaves room for one workgroup per CU).
-unsigned lds_eval_blocks();
+// Compute units of the current device. The persistent kernels (the sample
+// kernel and the LDS form, whose LDS leaves room for one workgroup per CU)
+// launch one workgroup per unit.
+unsigned compute_units();
 
 // Calls fn.template operator()<D>() for the compile-time row length D = d
 // (1 <= d <= kLdsMaxD).
@@ -835,7 +836,7 @@ hipError_t launch_bucket_eval(const Inst &I, const BucketGeom &B, const PassASha
         const bool buf = use_buffer(I), lr = lane_rows_fit(I);
         return dispatch_small_d(I.d, [&]<int D>() -> hipError_t {
 #define SNG_LDS_LAUNCH(BUF, LR)                                                              \
-    hipLaunchKernelGGL((k_bkt_eval_lds<D, BUF, LR, kQ>), dim3(lds_eval_blocks()),             \
+    hipLaunchKernelGGL((k_bkt_eval_lds<D, BUF, LR, kQ>), dim3(compute_units()),             \
                        dim3(kLdsThreads), lds, st, I, B)
             if (buf && lr) SNG_LDS_LAUNCH(true, true);
             else if (buf) SNG_LDS_LAUNCH(true, false);

@@ -11,7 +11,7 @@ hipError_t launch_bucket_eval_sweep(const Inst &I, const SweepArgs &S, const Buc
         const bool buf = use_buffer(I), lr = lane_rows_fit(I);
         return dispatch_small_d(I.d, [&]<int D>() -> hipError_t {
 #define SNG_LDS_LAUNCH(BUF, LR)                                                              \
-    hipLaunchKernelGGL((k_bkt_eval_lds_sweep<D, BUF, LR>), dim3(lds_eval_blocks()),           \
+    hipLaunchKernelGGL((k_bkt_eval_lds_sweep<D, BUF, LR>), dim3(compute_units()),           \
                        dim3(kLdsThreads), lds, st, I, B, S)
             if (buf && lr) SNG_LDS_LAUNCH(true, true);
             else if (buf) SNG_LDS_LAUNCH(true, false);
