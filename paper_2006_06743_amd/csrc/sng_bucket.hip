@@ -77,11 +77,12 @@ __device__ __forceinline__ uint32_t gen_exclusive(uint32_t v, uint32_t *wsum, ui
     return wsum[kGenWaves + w] + x - v;
 }
 
-// Record stage layout in LDS: per partner block J a pair of words at 2J
-// (count, then offset), for J <= NJ, the pair count rounded up to even so
-// that the stage that follows is 16-byte aligned. Block NJ collects the
-// slots that make no record (self pairs, words past m, calls past the
-// range), so every slot takes one unconditional counting step.
+// Record stage layout in LDS: the counts of partner blocks J <= NJ, then
+// their offsets (one word each, so consecutive blocks fall in consecutive
+// banks), each array rounded up to an even length so that the stage that
+// follows is 16-byte aligned. Block NJ collects the slots that make no
+// record (self pairs, words past m, calls past the range), so every slot
+// takes one unconditional counting step.
 __host__ __device__ __forceinline__ uint32_t gen_pairs(uint32_t NJ)
 {
     return (NJ + 2u) & ~1u;
@@ -96,7 +97,8 @@ __global__ __launch_bounds__(kGenThreads) void k_bkt_generate(Inst I, BucketGeom
     extern __shared__ __align__(16) uint32_t lds_u32[];
     __shared__ uint32_t wsum[2 * kGenWaves + 1];
     const uint32_t NJ = B.NJ;
-    uint32_t *cp = lds_u32;                         // [2 gen_pairs(NJ)]: count, offset
+    uint32_t *cnt = lds_u32;                        // [gen_pairs(NJ)]
+    uint32_t *pre = lds_u32 + gen_pairs(NJ);        // [gen_pairs(NJ)]
     uint32_t *stage = lds_u32 + 2 * gen_pairs(NJ);  // [kRangeSlots]
     const uint32_t tid = threadIdx.x;
     // Persistent: one workgroup per compute unit walks ranges blockIdx.x,
@@ -120,8 +122,8 @@ __global__ __launch_bounds__(kGenThreads) void k_bkt_generate(Inst I, BucketGeom
         const uint32_t ncalls = (uint32_t)(call_hi - call_lo);
         const uint32_t i0 = (uint32_t)(call_lo / I.C);
         const uint32_t c0 = (uint32_t)(call_lo - (uint64_t)i0 * I.C);
-        for (uint32_t k = tid; k < 2 * gen_pairs(NJ); k += kGenThreads)
-            cp[k] = 0;
+        for (uint32_t k = tid; k < gen_pairs(NJ); k += kGenThreads)
+            cnt[k] = 0;
         if (tid == 0) {
             B.start[2 * r + 0] = i0;  // source and call of the range's first call
             B.start[2 * r + 1] = c0;
@@ -161,7 +163,7 @@ __global__ __launch_bounds__(kGenThreads) void k_bkt_generate(Inst I, BucketGeom
         for (int w = 0; w < 4; ++w)
             thr[w] = I.m > (uint32_t)w ? I.m - (uint32_t)w : 0u;
         const uint32_t pmask = (1u << B.bshift) - 1u;
-        // key: byte offset of the block's pair << 16 | rank of the record in it
+        // key: byte offset of the block's offset word (4 J) << 16 | rank of the record in it
         uint32_t key[4 * kCallsPerThread], rec[4 * kCallsPerThread];
         // kAll: every call of the range is live and has four samples (m is a
         // multiple of 4), so only self pairs make no record
@@ -179,8 +181,8 @@ __global__ __launch_bounds__(kGenThreads) void k_bkt_generate(Inst I, BucketGeom
                                                    : mod_exact(W.w[w], I.n, I.inv_n);
                     const bool none = (j == ii) | (!kAll && cc4 >= thr[w]);
                     const uint32_t J = none ? NJ : (j >> B.bshift);
-                    const uint32_t rank = atomicAdd(cp + 2 * J, 1u);
-                    key[4 * c + w] = (J << 19) | rank;
+                    const uint32_t rank = atomicAdd(cnt + J, 1u);
+                    key[4 * c + w] = (J << 18) | rank;
                     rec[4 * c + w] = (j & pmask) | hb | ((uint32_t)w << w_shift);
                 }
                 cc += step_r;
@@ -204,16 +206,16 @@ __global__ __launch_bounds__(kGenThreads) void k_bkt_generate(Inst I, BucketGeom
         else
             count.template operator()<false>();
         __syncthreads();
-        const uint32_t v = tid < NJ ? cp[2 * tid] : 0u;
+        const uint32_t v = tid < NJ ? cnt[tid] : 0u;
         uint32_t total;
         const uint32_t ex = gen_exclusive(v, wsum, &total);
         if (tid < NJ) {
-            cp[2 * tid + 1] = ex;
+            pre[tid] = ex;
             *reinterpret_cast<uint2 *>(B.seg + (r * NJ + tid) * 2) = make_uint2(ex, v);
         }
         if (tid == 0) {
             // the slots without a record go past the records
-            cp[2 * NJ + 1] = total;
+            pre[NJ] = total;
             // self pairs: the range's sample slots (words below m of its calls;
             // the last call of a point has m - 4 (C - 1) of them) less its records
             const uint32_t wraps = (c0 + ncalls) / I.C;  // points whose last call is in the range
@@ -223,10 +225,10 @@ __global__ __launch_bounds__(kGenThreads) void k_bkt_generate(Inst I, BucketGeom
                 atomicAdd(B.hdr + 1, (unsigned long long)self);
         }
         __syncthreads();
-        const char *cpb = reinterpret_cast<const char *>(cp);
+        const char *preb = reinterpret_cast<const char *>(pre);
 #pragma unroll
         for (uint32_t k = 0; k < 4 * kCallsPerThread; ++k) {
-            const uint32_t base = *reinterpret_cast<const uint32_t *>(cpb + (key[k] >> 16) + 4);
+            const uint32_t base = *reinterpret_cast<const uint32_t *>(preb + (key[k] >> 16));
             stage[base + (key[k] & 0xFFFFu)] = rec[k];
         }
         __syncthreads();
