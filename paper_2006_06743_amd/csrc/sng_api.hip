@@ -1161,6 +1161,7 @@ static size_t sweep_ws_bytes(int64_t n, int64_t m, int32_t K, int32_t P)
     b = align_up(b + (size_t)n * (size_t)K * 4);  // level histograms
     b = align_up(b + z.chunks * 64 * 4);          // level codes per call
     b = align_up(b + (size_t)n * (size_t)P);      // core levels
+    b = align_up(b + (size_t)n * (size_t)P * 4);  // level links
     return b;
 }
 
@@ -1224,6 +1225,7 @@ int sng_dbscan_sweep(const float *X, int64_t n, int32_t d, int64_t ld, double s,
     S.hist = cv.take<uint32_t>((size_t)n * n_eps);
     S.codes = cv.take<uint32_t>(sizes_for(n, m).chunks * 64);
     S.kc = cv.take<uint8_t>((size_t)n * n_minpts);
+    S.link = cv.take<int32_t>((size_t)n * n_minpts);
     S.labels = labels;
     S.degrees = degrees;
     double band = 0.0;

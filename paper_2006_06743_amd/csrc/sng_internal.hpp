@@ -58,6 +58,7 @@ struct SweepArgs {
     uint32_t *hist;      // [n][K] accepted slots per point and level
     uint32_t *codes;     // per Philox call: four level codes (K = none)
     uint8_t *kc;         // [P][n] first core level (K = never)
+    int32_t *link;       // [P][n] level links set aside between two levels
     int32_t *labels;     // [P][K][n]
     uint32_t *degrees;   // [K][n] or null
 };

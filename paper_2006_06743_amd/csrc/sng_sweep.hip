@@ -206,8 +206,15 @@ __global__ __launch_bounds__(256) void k_sweep_hook(Inst I, SweepArgs S)
     }
 }
 
-// Level k -> k+1: join every core point of level k with its level-k root.
-__global__ __launch_bounds__(256) void k_sweep_propagate(Inst I, SweepArgs S, int k)
+// Level k -> k+1 in two launches. Level k is final. k_sweep_stars writes
+// each core point's level-k root into its level-k entry (level k is then
+// compressed) and into its level-(k+1) entry, so level k+1 starts from level
+// k's components with one plain store per point. The level-(k+1) links those
+// stores replace, unions born at k+1, go to `link`; k_sweep_relink joins them
+// again. Points that only become core at k+1 keep their links in place. One
+// union per core point instead (every point with its level-k root) made the
+// threads of a large component race compare-and-swaps on one shared root.
+__global__ __launch_bounds__(256) void k_sweep_stars(Inst I, SweepArgs S, int k)
 {
     const uint64_t total = (uint64_t)S.P * I.n;
     for (uint64_t u = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; u < total;
@@ -216,21 +223,46 @@ __global__ __launch_bounds__(256) void k_sweep_propagate(Inst I, SweepArgs S, in
         const uint32_t x = (uint32_t)(u - (uint64_t)p * I.n);
         if (S.kc[u] > k)
             continue;
-        const int32_t r = uf_find(level_labels(S, I.n, p, k), (int32_t)x);
-        if (r != (int32_t)x)
-            uf_unite(level_labels(S, I.n, p, k + 1), (int32_t)x, r);
+        // entries of level k only move to their roots here, so a walk
+        // through cached (possibly older) parents still ends at the root
+        int32_t *L0 = level_labels(S, I.n, p, k);
+        int32_t r = (int32_t)x, q = uf_ld(L0 + x);
+        while (q != r) {
+            r = q;
+            q = uf_ld(L0 + r);
+        }
+        uf_st(L0 + x, r);
+        int32_t *L1 = level_labels(S, I.n, p, k + 1);
+        S.link[u] = L1[x];
+        L1[x] = r;
     }
 }
 
-__global__ __launch_bounds__(256) void k_sweep_compress(Inst I, SweepArgs S)
+__global__ __launch_bounds__(256) void k_sweep_relink(Inst I, SweepArgs S, int k)
 {
-    const uint64_t total = (uint64_t)S.P * S.K * I.n;
+    const uint64_t total = (uint64_t)S.P * I.n;
     for (uint64_t u = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; u < total;
          u += (uint64_t)gridDim.x * blockDim.x) {
-        const uint64_t pk = u / I.n;
-        const uint32_t x = (uint32_t)(u - pk * I.n);
-        const int p = (int)(pk / S.K), k = (int)(pk - (uint64_t)p * S.K);
-        if (S.kc[(uint64_t)p * I.n + x] <= k) {
+        const int p = (int)(u / I.n);
+        const uint32_t x = (uint32_t)(u - (uint64_t)p * I.n);
+        if (S.kc[u] > k)
+            continue;
+        const int32_t e = S.link[u];
+        if (e != (int32_t)x)
+            uf_unite(level_labels(S, I.n, p, k + 1), (int32_t)x, e);
+    }
+}
+
+// The last level's roots (the levels below were compressed by k_sweep_stars).
+__global__ __launch_bounds__(256) void k_sweep_compress(Inst I, SweepArgs S)
+{
+    const uint64_t total = (uint64_t)S.P * I.n;
+    const int k = S.K - 1;
+    for (uint64_t u = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; u < total;
+         u += (uint64_t)gridDim.x * blockDim.x) {
+        const int p = (int)(u / I.n);
+        const uint32_t x = (uint32_t)(u - (uint64_t)p * I.n);
+        if (S.kc[u] <= k) {
             int32_t *L = level_labels(S, I.n, p, k);
             st_relaxed(L + x, uf_root(L, (int32_t)x));
         }
@@ -298,14 +330,14 @@ hipError_t launch_sweep(const Inst &I, const SweepArgs &S, const PassAShape &sh,
         if ((e = hipGetLastError()) != hipSuccess)
             return e;
     }
+    const unsigned grid = sweep_grid((uint64_t)S.P * I.n);
     for (int k = 0; k + 1 < S.K; ++k) {
-        hipLaunchKernelGGL(k_sweep_propagate, dim3(sweep_grid((uint64_t)S.P * I.n)), dim3(256), 0,
-                           st, I, S, k);
+        hipLaunchKernelGGL(k_sweep_stars, dim3(grid), dim3(256), 0, st, I, S, k);
+        hipLaunchKernelGGL(k_sweep_relink, dim3(grid), dim3(256), 0, st, I, S, k);
         if ((e = hipGetLastError()) != hipSuccess)
             return e;
     }
-    hipLaunchKernelGGL(k_sweep_compress, dim3(sweep_grid((uint64_t)S.P * S.K * I.n)), dim3(256),
-                       0, st, I, S);
+    hipLaunchKernelGGL(k_sweep_compress, dim3(grid), dim3(256), 0, st, I, S);
     if ((e = hipGetLastError()) != hipSuccess)
         return e;
     hipLaunchKernelGGL(k_sweep_borders, dim3(sweep_grid((uint64_t)S.P * I.n)), dim3(256), 0, st,
