@@ -16,6 +16,7 @@
 //   finalize  core labels are roots; a non-core point takes the prefix minimum
 //             of the offers up to k and the root of that core point.
 // labels[p][k] then equals the single run at (eps_k, MinPts_p).
+#include "sng_hook.hpp"
 #include "sng_pass_a.hpp"
 
 namespace sng {
@@ -211,9 +212,11 @@ __global__ __launch_bounds__(256) void k_sweep_hook(Inst I, SweepArgs S)
 // compressed) and into its level-(k+1) entry, so level k+1 starts from level
 // k's components with one plain store per point. The level-(k+1) links those
 // stores replace, unions born at k+1, go to `link`; k_sweep_relink joins them
-// again. Points that only become core at k+1 keep their links in place. One
-// union per core point instead (every point with its level-k root) made the
-// threads of a large component race compare-and-swaps on one shared root.
+// again (the links of a level run between few large components, hence the
+// verified hook). Points that only become core at k+1 keep their links in
+// place. One union per core point instead (every point with its level-k
+// root) made the threads of a large component race compare-and-swaps on one
+// shared root.
 __global__ __launch_bounds__(256) void k_sweep_stars(Inst I, SweepArgs S, int k)
 {
     const uint64_t total = (uint64_t)S.P * I.n;
@@ -249,7 +252,7 @@ __global__ __launch_bounds__(256) void k_sweep_relink(Inst I, SweepArgs S, int k
             continue;
         const int32_t e = S.link[u];
         if (e != (int32_t)x)
-            uf_unite(level_labels(S, I.n, p, k + 1), (int32_t)x, e);
+            uf_unite_verified(level_labels(S, I.n, p, k + 1), (int32_t)x, e);
     }
 }
 
