@@ -176,8 +176,17 @@ PassAShape shape_for(const Inst &I, const sng_config *cfg, bool bucketed = false
     int prefetch = cfg ? cfg->prefetch : 0;
     if (bucketed && prefetch == 0)
         prefetch = 4;
-    return resolve_shape(I.d, vec_ok, cfg ? cfg->lanes_per_pair : 0,
-                         cfg ? cfg->chunks_per_wave : 0, cfg ? cfg->stage_lds : 0, prefetch);
+    // Direct gathers default to eight chunks per wavefront, fewer when that
+    // would leave fewer than 4096 wavefronts (small instances: the 10k x 2
+    // call has 3907 chunks; one chunk per wave takes the call from 78 to
+    // 73 us).
+    int cpw = cfg ? cfg->chunks_per_wave : 0;
+    if (cpw == 0 && !bucketed) {
+        const uint64_t per = I.chunks / 4096;
+        cpw = per >= 8 ? 8 : (per >= 1 ? (int)per : 1);
+    }
+    return resolve_shape(I.d, vec_ok, cfg ? cfg->lanes_per_pair : 0, cpw,
+                         cfg ? cfg->stage_lds : 0, prefetch);
 }
 
 int check_cfg(const sng_config *cfg)
