@@ -88,6 +88,11 @@ __global__ __launch_bounds__(256) void k_core_init(Inst I)
 // few dense clusters cost more in failed compare-and-swaps than they hid.
 __global__ __launch_bounds__(256) void k_hook_mask(Inst I)
 {
+    // Without a core point no pair joins or offers anything, and the accept
+    // words (one bit per slot: 1.6 GB on the 5e6-point scene) need not be read.
+    if (I.cnt && __hip_atomic_load(I.cnt + kCntCore, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT) == 0ull)
+        return;  // grid-uniform
     const uint64_t words = I.chunks * 8ull;
     __shared__ uint16_t list[kHookRoundWords * 32];
     __shared__ uint32_t nlist;
