@@ -55,15 +55,17 @@ __device__ __forceinline__ void hook_pair(const Inst &I, uint32_t a, uint32_t b)
 // Block-local compaction of accept words: one round reads kHookRoundWords
 // words (one per thread of a 256-thread block, starting at w0, none at or
 // beyond hi) and lists their accepted slots in LDS, then every thread of
-// the block regenerates and hooks list entries. A wavefront therefore runs
-// about (accepted slots of the round) / 256 hooks in sequence instead of one
-// per (call, Philox word) position that any of its lanes accepted. w0 and hi
-// must be the same for the whole block. Entry: word offset in the round * 32
-// + bit (call in the word * 4 + Philox word).
+// the block regenerates list entries and hands each accepted pair (i, j) to
+// f. A wavefront therefore handles about (accepted slots of the round) / 256
+// pairs in sequence instead of one per (call, Philox word) position that any
+// of its lanes accepted. w0 and hi must be the same for the whole block.
+// Entry: word offset in the round * 32 + bit (call in the word * 4 + Philox
+// word).
 constexpr uint32_t kHookRoundWords = 256;
 
-__device__ __forceinline__ void hook_round(const Inst &I, uint64_t w0, uint64_t hi,
-                                           uint16_t *list, uint32_t *nlist)
+template <class F>
+__device__ __forceinline__ void accepted_round(const Inst &I, uint64_t w0, uint64_t hi,
+                                               uint16_t *list, uint32_t *nlist, F &&f)
 {
     if (threadIdx.x == 0)
         *nlist = 0;
@@ -82,9 +84,16 @@ __device__ __forceinline__ void hook_round(const Inst &I, uint64_t w0, uint64_t 
         const uint32_t i = (uint32_t)div_exact64(call, I.C, I.inv_C);
         const uint32_t c = (uint32_t)(call - (uint64_t)i * I.C);
         const Words4 W = philox10(c, i, I.key0, I.key1);
-        hook_pair(I, i, mod_exact(W.w[v & 3u], I.n, I.inv_n));
+        f(i, mod_exact(W.w[v & 3u], I.n, I.inv_n));
     }
     __syncthreads();  // the next round reuses the list and the count
+}
+
+// The hook of one round of accept words.
+__device__ __forceinline__ void hook_round(const Inst &I, uint64_t w0, uint64_t hi,
+                                           uint16_t *list, uint32_t *nlist)
+{
+    accepted_round(I, w0, hi, list, nlist, [&](uint32_t i, uint32_t j) { hook_pair(I, i, j); });
 }
 
 }  // namespace sng
