@@ -105,9 +105,9 @@ typedef struct {
  * floats: a block is the largest power of two of rows that fits 128 KB, when
  * that gives at most 1024 blocks) or reused from L2 (otherwise: at most 2^16
  * rows fitting 512 KB). It covers d <= 32 and at most 1024 partner blocks
- * (so n <= 2^25 at d = 3, n <= 2^23 at d = 16); auto picks it for d < 32
- * when X (n*d*4 bytes) exceeds 8 MB and the workspace holds its records,
- * direct gathers otherwise. stage_lds implies direct gathers.
+ * (so n <= 2^25 at d = 3, n <= 2^23 at d = 16); auto picks it when it
+ * covers the shape, X (n*d*4 bytes) exceeds 8 MB and the workspace holds its
+ * records, direct gathers otherwise. stage_lds implies direct gathers.
  * reuse_sample (sng_degrees and sng_dbscan only; SNG_EINVAL elsewhere and
  * with schedule 1 or stage_lds): skip drawing the partners and evaluate the
  * partner-block sample already in the workspace, as left by sng_sample or by
