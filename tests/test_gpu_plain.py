@@ -298,13 +298,17 @@ def test_cluster_entry_point_many_minpts(sng, orc):
     m = orc.samples_per_point(0.02, W.n)
     X = torch.from_numpy(W.X).cuda()
     deg, ws = sng.degrees(X, m, W.eps, W.seed)
-    for mp in [-1, 1, 3, 5, 12, 40]:
+    # 10**6: no point is core, though slots are accepted (the hook returns at
+    # once); the 3 after it must hook again on the same workspace
+    for mp in [-1, 1, 3, 5, 12, 40, 10**6, 3]:
         lab = sng.cluster(X, m, W.eps, W.seed, mp, deg, ws)
         torch.cuda.synchronize()
         ref = orc.dbscan(W.X, W.eps, mp, W.seed, m=m)
         assert_same(lab.cpu().numpy(), deg.cpu().numpy().view(np.uint32), ref, "MinPts=%d" % mp)
         st = sng.stats(ws)
         assert st.n_core == ref.n_core and st.n_clusters == ref.n_clusters
+        if mp == 10**6:
+            assert ref.n_core == 0 and ref.accepted > 0 and (lab.cpu().numpy() == -1).all()
 
 
 def compact_on_gpu(sng, labels):
