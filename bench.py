@@ -382,7 +382,10 @@ def cfg_sweep(sng, torch, wl, reps):
             "speedup_vs_128_calls": t_all / t_sweep["median"],
             "labels_identical": all(same), "grid_points_identical": sum(same),
             "roofline_single_plain_call": {"bound": "hbm", "algorithmic_bytes": alg,
-                                           "frac": frac(alg, single)[1]}}
+                                           "frac": frac(alg, single)[1],
+                                           "note": "one 128-byte row per slot over the call's "
+                                                   "time; partner blocks serve most rows from "
+                                                   "L2, so this can exceed 1"}}
 
 
 def cfg_batch(sng, torch, wl, reps):
