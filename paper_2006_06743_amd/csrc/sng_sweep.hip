@@ -122,13 +122,29 @@ __global__ __launch_bounds__(256) void k_sweep_levels(Inst I, SweepArgs S)
         for (int p = 0; p < S.P; ++p)
             kc[p] = (uint8_t)S.K;
         uint64_t run = 0;
-        for (int k = 0; k < S.K; ++k) {
-            run += S.hist[i * S.K + k];
+        auto level = [&](int k, uint32_t h) {
+            run += h;
             if (S.degrees)
                 S.degrees[(uint64_t)k * I.n + i] = (uint32_t)run;
             for (int p = 0; p < S.P; ++p)
                 if (kc[p] == S.K && (int64_t)run >= (int64_t)S.c.min_pts[p])
                     kc[p] = (uint8_t)k;
+        };
+        if ((S.K & 3) == 0) {  // the row is 16-byte aligned: four levels per load
+            const uint4 *h4 = reinterpret_cast<const uint4 *>(S.hist + i * S.K);
+            uint4 nx = h4[0];
+            for (int k = 0; k < S.K; k += 4) {
+                const uint4 h = nx;
+                if (k + 4 < S.K)
+                    nx = h4[(k >> 2) + 1];
+                level(k, h.x);
+                level(k + 1, h.y);
+                level(k + 2, h.z);
+                level(k + 3, h.w);
+            }
+        } else {
+            for (int k = 0; k < S.K; ++k)
+                level(k, S.hist[i * S.K + k]);
         }
         for (int p = 0; p < S.P; ++p) {
             S.kc[(uint64_t)p * I.n + i] = kc[p];
