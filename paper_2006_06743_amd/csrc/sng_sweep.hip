@@ -297,13 +297,29 @@ __global__ __launch_bounds__(256) void k_sweep_borders(Inst I, SweepArgs S)
          u += (uint64_t)gridDim.x * blockDim.x) {
         const int p = (int)(u / I.n);
         const uint32_t x = (uint32_t)(u - (uint64_t)p * I.n);
-        const int kc = S.kc[u];
+        const int kend = min((int)S.kc[u], S.K);
         int32_t best = kNoCore;
-        for (int k = 0; k < kc && k < S.K; ++k) {
-            int32_t *L = level_labels(S, I.n, p, k);
-            const int32_t offer = L[x];
-            best = min(best, offer);
-            L[x] = (best == kNoCore) ? -1 : L[best];
+        // eight levels at a time: their offers, then their labels, are loaded
+        // together (x is not core below kend, so no thread reads L[x] there)
+        for (int k0 = 0; k0 < kend; k0 += 8) {
+            int32_t off[8], bst[8], lab[8];
+#pragma unroll
+            for (int t = 0; t < 8; ++t)
+                off[t] = (k0 + t < kend) ? level_labels(S, I.n, p, k0 + t)[x] : kNoCore;
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                best = min(best, off[t]);
+                bst[t] = best;
+            }
+#pragma unroll
+            for (int t = 0; t < 8; ++t)
+                lab[t] = (k0 + t < kend && bst[t] != kNoCore)
+                             ? level_labels(S, I.n, p, k0 + t)[bst[t]]
+                             : -1;
+#pragma unroll
+            for (int t = 0; t < 8; ++t)
+                if (k0 + t < kend)
+                    level_labels(S, I.n, p, k0 + t)[x] = lab[t];
         }
     }
 }
